@@ -1,0 +1,179 @@
+/*
+ * liblpsift: LP-SIFT feature front end on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the local-peak scale-invariant feature transform of Li, Wang,
+ * Zhao and Zhao ("Local-peak scale-invariant feature transform for fast and
+ * random image stitching"): keypoints are the maximum and the minimum of every
+ * L x L window at several window sizes L (Sec. 2.2), each is described by a
+ * d x d x 8 SIFT histogram (Sec. 2.3), and descriptors of a reference image are
+ * matched against those of a registered image by Euclidean distance (Sec. 2.4).
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE pointers unless the comment says "host".
+ *  - The caller owns every buffer; the library never allocates device memory.
+ *  - Every call validates all arguments on the host first and returns
+ *    LPSIFT_EINVAL / LPSIFT_ECAPACITY / LPSIFT_EUNSUPPORTED without touching the
+ *    GPU. Valid calls enqueue kernels on `stream` (a hipStream_t; NULL is the
+ *    null stream) and return without synchronising; a kernel launch failure
+ *    returns LPSIFT_EHIP. Device faults surface at the caller's next sync.
+ *  - No call aborts or throws. Calls on different streams may run concurrently
+ *    as long as their output and workspace buffers do not overlap.
+ *  - Images are 8-bit grayscale, row-major with a row pitch in bytes;
+ *    x is the column and y the row.
+ */
+#ifndef LPSIFT_H
+#define LPSIFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LPSIFT_OK = 0,
+    LPSIFT_EINVAL = -1,       /* a null pointer, a bad size or parameter    */
+    LPSIFT_ECAPACITY = -2,    /* an output or workspace buffer is too small */
+    LPSIFT_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+    LPSIFT_EUNSUPPORTED = -4  /* valid for the method, not built on the GPU */
+};
+
+#define LPSIFT_MAX_SCALES 8
+#define LPSIFT_DESC_DIM 128   /* d x d x 8 with d = 4 */
+
+/* Method parameters (Sec. 2.2-2.3).
+ *  n_scales  number of window sizes, 1..LPSIFT_MAX_SCALES
+ *  L         window sides, strictly ascending, L[0] >= 4. On the GPU each L must
+ *            divide the next and the largest must be <= 256 (nested windows).
+ *  d         subregions per side of the descriptor square; only 4 is built.
+ *  beta0     Eq. 3-4 size factor; <= 0 selects the largest admissible value
+ *            (1/d) sqrt(Lmin/Lmax), for which w = d w_s <= L at every scale. */
+typedef struct lpsift_params {
+    int32_t n_scales;
+    int32_t L[LPSIFT_MAX_SCALES];
+    int32_t d;
+    float beta0;
+} lpsift_params;
+
+/* One 8-bit grayscale image in device memory: height rows of width bytes,
+ * row r starting at data + r * pitch (pitch >= width). */
+typedef struct lpsift_image {
+    const uint8_t* data;
+    int32_t height;
+    int32_t width;
+    int64_t pitch;
+} lpsift_image;
+
+/* Keypoints of one image, structure of arrays, `capacity` entries each.
+ * Slot layout (fixed, no compaction): scales in the order of params.L; within
+ * scale s, window (by, bx) of the ceil(H/L) x ceil(W/L) grid owns slots
+ * base_s + 2 (by ceil(W/L) + bx) (its maximum) and that + 1 (its minimum),
+ * base_s = sum over earlier scales of 2 ceil(H/L) ceil(W/L).
+ *  x, y      pixel position of the extremum
+ *  scale     index into params.L
+ *  type      +1 maximum, -1 minimum
+ *  value     intensity at the extremum
+ *  contrast  |value - window mean| / 255, window mean over the clipped window */
+typedef struct lpsift_keypoints {
+    int32_t* x;
+    int32_t* y;
+    uint8_t* scale;
+    int8_t* type;
+    uint8_t* value;
+    float* contrast;
+    int64_t capacity;
+} lpsift_keypoints;
+
+/* Matching parameters (Sec. 2.4, Eq. 6).
+ *  ratio       a query is kept when d1 < ratio * d2 (compared in double)
+ *  abs_thresh  ... and d1 < abs_thresh (the Delta_s of Eq. 6; +inf disables it)
+ *  precision   0 = FP32 distance contraction (the only one built so far)
+ *  b_chunks    candidate-range split of the contraction; 0 = automatic */
+typedef struct lpsift_match_params {
+    double ratio;
+    float abs_thresh;
+    int32_t precision;
+    int32_t b_chunks;
+} lpsift_match_params;
+
+/* Library version as 10000*major + 100*minor + patch. Host only. */
+int lpsift_version(void);
+
+/* Human-readable name of a status code. Host only, static storage. */
+const char* lpsift_status_string(int status);
+
+/* Number of keypoints of an image (one maximum and one minimum per window of
+ * every scale, partial windows at the right and bottom edges included):
+ * 2 * sum_s ceil(height/L_s) ceil(width/L_s). Host only, pure.
+ * Returns -1 for invalid arguments. */
+int64_t lpsift_num_keypoints(int32_t height, int32_t width, const lpsift_params* params);
+
+/* Feature point detection (Sec. 2.2, Eq. 2) with the linear background of
+ * Eq. 1 taken as an infinitesimal tie-break: among equal intensities the
+ * maximum of a window is the pixel with the largest raster index y*W + x and
+ * the minimum the one with the smallest.
+ *  imgs    host array of n_images image descriptors (device pixel data)
+ *  out     host array of n_images keypoint buffers, each with capacity >=
+ *          lpsift_num_keypoints(image); every slot is written.
+ * Errors: EINVAL (null pointer, n_images < 1, empty image, pitch < width, bad
+ * params), ECAPACITY (capacity too small), EUNSUPPORTED (L set not nested or
+ * Lmax > 256), EHIP. */
+int lpsift_detect(const lpsift_image* imgs, int32_t n_images, const lpsift_params* params,
+                  const lpsift_keypoints* out, void* stream);
+
+/* Device workspace, in bytes, that lpsift_describe needs for these images. */
+size_t lpsift_describe_workspace_size(const lpsift_image* imgs, int32_t n_images,
+                                      const lpsift_params* params);
+
+/* Orientation assignment and description (Sec. 2.3, Eq. 3-5) of every keypoint
+ * slot written by lpsift_detect for the same images and params.
+ * Gradients (Eq. 5): a = I(y+1,x) - I(y-1,x), b = I(y,x+1) - I(y,x-1),
+ * magnitude sqrt(a^2+b^2), angle atan2(a, b); pixels on the image border have
+ * no gradient. With w_s = beta L (Eq. 3):
+ *  theta   dominant orientation in radians: 36-bin histogram of magnitudes
+ *          weighted by a Gaussian of sigma w_s/2 over the disc of radius
+ *          round(1.5 w_s), linear votes between bins centred at multiples of
+ *          10 degrees, one circular [1 4 6 4 1]/16 smoothing, argmax (lowest bin
+ *          on ties) refined by a parabola through the peak and its neighbours.
+ *  desc    [n_kp][128] row-major: offsets rotated by -theta and divided by w_s,
+ *          cells centred at -1.5..1.5, Gaussian weight of sigma 2 cells,
+ *          trilinear votes into 4 x 4 cells x 8 direction bins (bin o centred at
+ *          45 o degrees from theta), element (cy*4 + cx)*8 + o; then normalised,
+ *          clipped at 0.2 and normalised again (all zeros for a flat patch).
+ *  kps        host array of n_images keypoint buffers written by lpsift_detect
+ *  workspace  device buffer of ws_bytes >= lpsift_describe_workspace_size()
+ *  theta      host array of n_images device pointers to float[n_kp]
+ *  desc       host array of n_images device pointers to float[n_kp * 128]
+ * Errors: EINVAL, ECAPACITY (keypoint capacity or workspace), EUNSUPPORTED
+ * (d != 4), EHIP. */
+int lpsift_describe(const lpsift_image* imgs, int32_t n_images, const lpsift_keypoints* kps,
+                    const lpsift_params* params, void* workspace, size_t ws_bytes,
+                    float* const* theta, float* const* desc, void* stream);
+
+/* Device workspace, in bytes, that lpsift_match needs. nA, nB: host arrays of
+ * n_pairs descriptor counts. */
+size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t n_pairs,
+                                   const lpsift_match_params* mp);
+
+/* Descriptor matching (Sec. 2.4, Eq. 6) for n_pairs independent pairs. For each
+ * reference descriptor i of pair p: j1 = the registered descriptor nearest in
+ * Euclidean distance (lowest index on ties), d1 its distance and d2 the second
+ * smallest distance over the other registered descriptors (+inf if there is
+ * none). match[i] = j1 when d1 < ratio * d2 and d1 < abs_thresh, else -1.
+ * d1 and d2 are FP32 distances sqrt(sum (a-b)^2) recomputed directly for the
+ * best candidates of an FP32 matrix-core contraction.
+ *  descA, descB  host arrays of n_pairs device pointers to float[n][128]
+ *  nA, nB        host arrays of n_pairs counts (nA >= 0, nB >= 0)
+ *  match, d1, d2 host arrays of n_pairs device pointers to int32/float[nA]
+ * Errors: EINVAL, ECAPACITY (workspace), EUNSUPPORTED (precision != 0), EHIP. */
+int lpsift_match(const float* const* descA, const int64_t* nA, const float* const* descB,
+                 const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
+                 void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
+                 float* const* d2, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPSIFT_H */

@@ -1,0 +1,282 @@
+"""LP-SIFT on AMD Instinct MI355X: Python binding of liblpsift.
+
+Argument marshalling only. Every step of the path (detection, orientation,
+description, matching) runs in the HIP kernels of liblpsift.so; PyTorch
+supplies device memory and the current stream. There is no CPU fallback: if the
+library is not built, every call raises.
+
+    import paper_2405_08578_amd as lp
+    P = lp.Params([16, 32, 64, 128])
+    kp = lp.detect([img_a, img_b], P)              # uint8 [H, W] CUDA tensors
+    theta, desc = lp.describe([img_a, img_b], kp, P)
+    m = lp.match([desc[0]], [desc[1]], ratio=0.8)[0]
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, List, Optional, Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblpsift.so")
+
+LPSIFT_OK = 0
+LPSIFT_EINVAL = -1
+LPSIFT_ECAPACITY = -2
+LPSIFT_EHIP = -3
+LPSIFT_EUNSUPPORTED = -4
+MAX_SCALES = 8
+DESC_DIM = 128
+
+c_i32, c_i64, c_f32, c_f64, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                    ctypes.c_double, ctypes.c_void_p)
+
+
+class lpsift_params(ctypes.Structure):
+    _fields_ = [("n_scales", c_i32), ("L", c_i32 * MAX_SCALES), ("d", c_i32), ("beta0", c_f32)]
+
+
+class lpsift_image(ctypes.Structure):
+    _fields_ = [("data", c_vp), ("height", c_i32), ("width", c_i32), ("pitch", c_i64)]
+
+
+class lpsift_keypoints(ctypes.Structure):
+    _fields_ = [("x", c_vp), ("y", c_vp), ("scale", c_vp), ("type", c_vp), ("value", c_vp),
+                ("contrast", c_vp), ("capacity", c_i64)]
+
+
+class lpsift_match_params(ctypes.Structure):
+    _fields_ = [("ratio", c_f64), ("abs_thresh", c_f32), ("precision", c_i32),
+                ("b_chunks", c_i32)]
+
+
+EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
+           "lpsift_describe_workspace_size", "lpsift_describe", "lpsift_match_workspace_size",
+           "lpsift_match")
+
+_lib = None
+
+
+class LpsiftError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn} failed: {status} ({status_string(status)})")
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblpsift.so and declare its C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblpsift.so is not built ({path}); run "
+                           "`python -m paper_2405_08578_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.lpsift_version.restype = ctypes.c_int
+    lib.lpsift_version.argtypes = []
+    lib.lpsift_status_string.restype = ctypes.c_char_p
+    lib.lpsift_status_string.argtypes = [ctypes.c_int]
+    lib.lpsift_num_keypoints.restype = c_i64
+    lib.lpsift_num_keypoints.argtypes = [c_i32, c_i32, P(lpsift_params)]
+    lib.lpsift_detect.restype = ctypes.c_int
+    lib.lpsift_detect.argtypes = [P(lpsift_image), c_i32, P(lpsift_params), P(lpsift_keypoints), c_vp]
+    lib.lpsift_describe_workspace_size.restype = ctypes.c_size_t
+    lib.lpsift_describe_workspace_size.argtypes = [P(lpsift_image), c_i32, P(lpsift_params)]
+    lib.lpsift_describe.restype = ctypes.c_int
+    lib.lpsift_describe.argtypes = [P(lpsift_image), c_i32, P(lpsift_keypoints), P(lpsift_params),
+                                    c_vp, ctypes.c_size_t, P(c_vp), P(c_vp), c_vp]
+    lib.lpsift_match_workspace_size.restype = ctypes.c_size_t
+    lib.lpsift_match_workspace_size.argtypes = [P(c_i64), P(c_i64), c_i32, P(lpsift_match_params)]
+    lib.lpsift_match.restype = ctypes.c_int
+    lib.lpsift_match.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
+                                 P(lpsift_match_params), c_vp, ctypes.c_size_t, P(c_vp), P(c_vp),
+                                 P(c_vp), c_vp]
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().lpsift_status_string(int(status)).decode()
+
+
+def _check(fn: str, status: int):
+    if status != LPSIFT_OK:
+        raise LpsiftError(fn, status)
+
+
+class Params:
+    """Window sizes L (Sec. 2.2), descriptor subregions d and beta0 (Eq. 3-4;
+    <= 0 picks the largest admissible value)."""
+
+    def __init__(self, L: Sequence[int], d: int = 4, beta0: float = 0.0):
+        if not 1 <= len(L) <= MAX_SCALES:
+            raise ValueError("1..8 window sizes")
+        self.L = [int(v) for v in L]
+        self.d = int(d)
+        self.beta0 = float(beta0)
+
+    def c(self) -> lpsift_params:
+        p = lpsift_params()
+        p.n_scales = len(self.L)
+        for i, v in enumerate(self.L):
+            p.L[i] = v
+        p.d = self.d
+        p.beta0 = self.beta0
+        return p
+
+
+def num_keypoints(h: int, w: int, params: Params) -> int:
+    n = load().lpsift_num_keypoints(h, w, ctypes.byref(params.c()))
+    if n < 0:
+        raise ValueError("invalid image size or parameters")
+    return int(n)
+
+
+def _stream(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _image(t) -> lpsift_image:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.dim() != 2 or not t.is_cuda:
+        raise ValueError("images must be 2-D uint8 CUDA tensors")
+    if t.stride(1) != 1:
+        raise ValueError("image rows must be contiguous")
+    im = lpsift_image()
+    im.data = t.data_ptr()
+    im.height, im.width = t.shape
+    im.pitch = t.stride(0)
+    return im
+
+
+def _images(images) -> "ctypes.Array":
+    arr = (lpsift_image * len(images))()
+    for i, t in enumerate(images):
+        arr[i] = _image(t)
+    return arr
+
+
+def empty_keypoints(n: int, device) -> Dict[str, "object"]:
+    import torch
+    return {"x": torch.empty(n, dtype=torch.int32, device=device),
+            "y": torch.empty(n, dtype=torch.int32, device=device),
+            "scale": torch.empty(n, dtype=torch.uint8, device=device),
+            "type": torch.empty(n, dtype=torch.int8, device=device),
+            "value": torch.empty(n, dtype=torch.uint8, device=device),
+            "contrast": torch.empty(n, dtype=torch.float32, device=device)}
+
+
+def _kp_struct(kp) -> lpsift_keypoints:
+    k = lpsift_keypoints()
+    for f in ("x", "y", "scale", "type", "value", "contrast"):
+        setattr(k, f, kp[f].data_ptr())
+    k.capacity = kp["x"].numel()
+    return k
+
+
+def _kps(kps) -> "ctypes.Array":
+    arr = (lpsift_keypoints * len(kps))()
+    for i, kp in enumerate(kps):
+        arr[i] = _kp_struct(kp)
+    return arr
+
+
+def detect(images, params: Params, out=None, stream=None) -> List[Dict[str, "object"]]:
+    """Window maxima and minima of every image at every L (fixed slots)."""
+    lib = load()
+    imgs = _images(images)
+    if out is None:
+        out = [empty_keypoints(num_keypoints(t.shape[0], t.shape[1], params), t.device)
+               for t in images]
+    p = params.c()
+    _check("lpsift_detect", lib.lpsift_detect(imgs, len(images), ctypes.byref(p), _kps(out),
+                                              _stream(stream)))
+    return out
+
+
+def describe_workspace_size(images, params: Params) -> int:
+    return int(load().lpsift_describe_workspace_size(_images(images), len(images),
+                                                     ctypes.byref(params.c())))
+
+
+def describe(images, kps, params: Params, workspace=None, theta=None, desc=None, stream=None):
+    """Orientation (radians) and 128-d descriptors of every keypoint slot."""
+    import torch
+    lib = load()
+    imgs = _images(images)
+    dev = images[0].device
+    n = len(images)
+    if theta is None:
+        theta = [torch.empty(kp["x"].numel(), dtype=torch.float32, device=dev) for kp in kps]
+    if desc is None:
+        desc = [torch.empty((kp["x"].numel(), DESC_DIM), dtype=torch.float32, device=dev)
+                for kp in kps]
+    p = params.c()
+    need = int(lib.lpsift_describe_workspace_size(imgs, n, ctypes.byref(p)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    th = (c_vp * n)(*[t.data_ptr() for t in theta])
+    de = (c_vp * n)(*[t.data_ptr() for t in desc])
+    _check("lpsift_describe", lib.lpsift_describe(imgs, n, _kps(kps), ctypes.byref(p),
+                                                  workspace.data_ptr(), workspace.numel(), th, de,
+                                                  _stream(stream)))
+    return theta, desc
+
+
+def match_params(ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
+                 b_chunks: int = 0) -> lpsift_match_params:
+    mp = lpsift_match_params()
+    mp.ratio = ratio
+    mp.abs_thresh = abs_thresh
+    mp.precision = precision
+    mp.b_chunks = b_chunks
+    return mp
+
+
+def match_workspace_size(nA: Sequence[int], nB: Sequence[int], mp: lpsift_match_params) -> int:
+    n = len(nA)
+    return int(load().lpsift_match_workspace_size((c_i64 * n)(*nA), (c_i64 * n)(*nB), n,
+                                                  ctypes.byref(mp)))
+
+
+def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
+          b_chunks: int = 0, workspace=None, out=None, stream=None) -> List[Dict[str, "object"]]:
+    """Nearest neighbour of every row of descA[p] among descB[p] with the ratio
+    test, for every pair p."""
+    import torch
+    lib = load()
+    n = len(descA)
+    if len(descB) != n or n < 1:
+        raise ValueError("descA and descB must be equal-length non-empty lists")
+    for t in list(descA) + list(descB):
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != DESC_DIM or not t.is_cuda \
+                or not t.is_contiguous():
+            raise ValueError("descriptors must be contiguous float32 CUDA tensors [n, 128]")
+    dev = descA[0].device
+    mp = match_params(ratio, abs_thresh, precision, b_chunks)
+    nA = [int(t.shape[0]) for t in descA]
+    nB = [int(t.shape[0]) for t in descB]
+    need = match_workspace_size(nA, nB, mp)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = [{"match": torch.empty(a, dtype=torch.int32, device=dev),
+                "d1": torch.empty(a, dtype=torch.float32, device=dev),
+                "d2": torch.empty(a, dtype=torch.float32, device=dev)} for a in nA]
+    ptr = lambda ts: (c_vp * n)(*[t.data_ptr() for t in ts])
+    _check("lpsift_match", lib.lpsift_match(
+        ptr(descA), (c_i64 * n)(*nA), ptr(descB), (c_i64 * n)(*nB), n, ctypes.byref(mp),
+        workspace.data_ptr(), workspace.numel(), ptr([o["match"] for o in out]),
+        ptr([o["d1"] for o in out]), ptr([o["d2"] for o in out]), _stream(stream)))
+    return out
+
+
+def features(images, params: Params, stream=None):
+    """detect + describe: returns (keypoints, theta, desc), lists per image."""
+    kps = detect(images, params, stream=stream)
+    theta, desc = describe(images, kps, params, stream=stream)
+    return kps, theta, desc

@@ -1,0 +1,216 @@
+// C-ABI entry points of liblpsift: argument validation on the host, then the
+// launchers of detect.hip, describe.hip and match.hip. No call allocates device
+// memory, synchronises, throws or aborts.
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace lpsift {
+
+int make_geometry(const lpsift_params* p, Geometry* g)
+{
+    if (!p || !g) return LPSIFT_EINVAL;
+    if (p->n_scales < 1 || p->n_scales > LPSIFT_MAX_SCALES) return LPSIFT_EINVAL;
+    if (p->d < 1 || p->d > 16) return LPSIFT_EINVAL;
+    if (!(p->beta0 <= 0.0f || std::isfinite(p->beta0))) return LPSIFT_EINVAL;
+    if (std::isnan(p->beta0)) return LPSIFT_EINVAL;
+    for (int s = 0; s < p->n_scales; ++s) {
+        if (p->L[s] < 4 || p->L[s] > 65536) return LPSIFT_EINVAL;
+        if (s > 0 && p->L[s] <= p->L[s - 1]) return LPSIFT_EINVAL;
+    }
+    if (p->d != 4) return LPSIFT_EUNSUPPORTED;
+    // nested windows, largest at most 128: what the tile kernel is built for
+    for (int s = 1; s < p->n_scales; ++s)
+        if (p->L[s] % p->L[s - 1] != 0) return LPSIFT_EUNSUPPORTED;
+    const int Lmin = p->L[0], Lmax = p->L[p->n_scales - 1];
+    if (Lmax > 128) return LPSIFT_EUNSUPPORTED;
+
+    // Eq. 3-4: beta = beta0 (L/Lmax)^(-1/2), w_s = beta L; default beta0 is the
+    // largest value with w = d w_s <= L at every scale
+    const double beta0 = (p->beta0 > 0.0f) ? (double)p->beta0
+                                            : (1.0 / p->d) * std::sqrt((double)Lmin / (double)Lmax);
+    const double log2e = 1.4426950408889634;
+    g->n_scales = p->n_scales;
+    int entries = 0;
+    for (int s = 0; s < p->n_scales; ++s) {
+        const double L = p->L[s];
+        const double ws = beta0 * std::pow(L / (double)Lmax, -0.5) * L;
+        const double half = 0.5 * (p->d + 1) * ws;
+        const double r2d = 2.0 * half * half;
+        const double ro = std::floor(1.5 * ws + 0.5);
+        if (!(ws > 0.0) || r2d > 4.0e6) return LPSIFT_EINVAL;   // support radius <= 2000 px
+        ScaleGeom& G = g->s[s];
+        g->L[s] = p->L[s];
+        G.ws = (float)ws;
+        G.inv_ws = (float)(1.0 / ws);
+        G.k_orient = (float)(-log2e / (2.0 * (0.5 * ws) * (0.5 * ws)));
+        G.k_desc = (float)(-log2e / (2.0 * (0.5 * p->d) * (0.5 * p->d) * ws * ws));
+        G.r2_orient = (int)(ro * ro);
+        G.r2_desc = (int)std::floor(r2d);
+        G.off_orient = entries;
+        G.n_orient = disc_count(G.r2_orient);
+        entries += G.n_orient;
+        G.off_desc = entries;
+        G.n_desc = disc_count(G.r2_desc);
+        entries += G.n_desc;
+    }
+    g->table_entries = entries;
+    return LPSIFT_OK;
+}
+
+}  // namespace lpsift
+
+using namespace lpsift;
+
+namespace {
+
+int check_images(const lpsift_image* imgs, int32_t n)
+{
+    if (!imgs || n < 1) return LPSIFT_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const lpsift_image& im = imgs[i];
+        if (!im.data || im.height < 1 || im.width < 1 || im.pitch < im.width) return LPSIFT_EINVAL;
+        if (im.height > 32767 || im.width > 32767) return LPSIFT_EINVAL;
+    }
+    return LPSIFT_OK;
+}
+
+int check_keypoints(const lpsift_image* imgs, int32_t n, const lpsift_keypoints* kps,
+                    const lpsift_params* p)
+{
+    if (!kps) return LPSIFT_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const lpsift_keypoints& k = kps[i];
+        if (!k.x || !k.y || !k.scale || !k.type || !k.value || !k.contrast) return LPSIFT_EINVAL;
+        if (k.capacity < lpsift_num_keypoints(imgs[i].height, imgs[i].width, p))
+            return LPSIFT_ECAPACITY;
+    }
+    return LPSIFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lpsift_version(void) { return 100; }
+
+const char* lpsift_status_string(int status)
+{
+    switch (status) {
+    case LPSIFT_OK: return "ok";
+    case LPSIFT_EINVAL: return "invalid argument";
+    case LPSIFT_ECAPACITY: return "buffer too small";
+    case LPSIFT_EHIP: return "HIP runtime or launch failure";
+    case LPSIFT_EUNSUPPORTED: return "not supported on the GPU path";
+    default: return "unknown status";
+    }
+}
+
+int64_t lpsift_num_keypoints(int32_t height, int32_t width, const lpsift_params* p)
+{
+    if (!p || height < 1 || width < 1 || p->n_scales < 1 || p->n_scales > LPSIFT_MAX_SCALES)
+        return -1;
+    int64_t n = 0;
+    for (int s = 0; s < p->n_scales; ++s) {
+        if (p->L[s] < 1) return -1;
+        n += 2 * n_windows(height, p->L[s]) * n_windows(width, p->L[s]);
+    }
+    return n;
+}
+
+int lpsift_detect(const lpsift_image* imgs, int32_t n, const lpsift_params* p,
+                  const lpsift_keypoints* out, void* stream)
+{
+    Geometry g;
+    int st = make_geometry(p, &g);
+    if (st == LPSIFT_EINVAL) return st;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    const int stk = check_keypoints(imgs, n, out, p);
+    if (stk != LPSIFT_OK) return stk;
+    if (st != LPSIFT_OK) return st;
+    return launch_detect(imgs, n, g, out, static_cast<hipStream_t>(stream));
+}
+
+size_t lpsift_describe_workspace_size(const lpsift_image* imgs, int32_t n, const lpsift_params* p)
+{
+    Geometry g;
+    if (make_geometry(p, &g) != LPSIFT_OK || check_images(imgs, n) != LPSIFT_OK) return 0;
+    return describe_workspace_bytes(imgs, n, g);
+}
+
+int lpsift_describe(const lpsift_image* imgs, int32_t n, const lpsift_keypoints* kps,
+                    const lpsift_params* p, void* workspace, size_t ws_bytes,
+                    float* const* theta, float* const* desc, void* stream)
+{
+    Geometry g;
+    int st = make_geometry(p, &g);
+    if (st == LPSIFT_EINVAL) return st;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    if (!theta || !desc || !workspace) return LPSIFT_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!theta[i] || !desc[i]) return LPSIFT_EINVAL;
+    const int stk = check_keypoints(imgs, n, kps, p);
+    if (stk != LPSIFT_OK) return stk;
+    if (st != LPSIFT_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    if (ws_bytes < describe_workspace_bytes(imgs, n, g)) return LPSIFT_ECAPACITY;
+    return launch_describe(imgs, n, kps, g, workspace, theta, desc,
+                           static_cast<hipStream_t>(stream));
+}
+
+static int check_match_params(const lpsift_match_params* mp)
+{
+    if (!mp) return LPSIFT_EINVAL;
+    if (!(mp->ratio > 0.0) || !std::isfinite(mp->ratio)) return LPSIFT_EINVAL;
+    if (std::isnan(mp->abs_thresh) || !(mp->abs_thresh > 0.0f)) return LPSIFT_EINVAL;
+    if (mp->b_chunks < 0 || mp->b_chunks > 16) return LPSIFT_EINVAL;
+    if (mp->precision < 0 || mp->precision > 2) return LPSIFT_EINVAL;
+    if (mp->precision != 0) return LPSIFT_EUNSUPPORTED;
+    return LPSIFT_OK;
+}
+
+size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t n_pairs,
+                                   const lpsift_match_params* mp)
+{
+    if (!nA || !nB || n_pairs < 1 || check_match_params(mp) != LPSIFT_OK) return 0;
+    size_t b = 0;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (nA[i] < 0 || nB[i] < 0) return 0;
+        b += align_up(match_workspace_bytes(nA[i], nB[i], mp), 256);
+    }
+    return b;
+}
+
+int lpsift_match(const float* const* descA, const int64_t* nA, const float* const* descB,
+                 const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
+                 void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
+                 float* const* d2, void* stream)
+{
+    const int sp = check_match_params(mp);
+    if (sp == LPSIFT_EINVAL) return sp;
+    if (!descA || !nA || !descB || !nB || n_pairs < 1 || !match || !d1 || !d2)
+        return LPSIFT_EINVAL;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (nA[i] < 0 || nB[i] < 0 || nA[i] > INT32_MAX || nB[i] > INT32_MAX) return LPSIFT_EINVAL;
+        if (nA[i] > 0 && (!descA[i] || !match[i] || !d1[i] || !d2[i])) return LPSIFT_EINVAL;
+        if (nB[i] > 0 && !descB[i]) return LPSIFT_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(descA[i]) | reinterpret_cast<uintptr_t>(descB[i])) & 15u)
+            return LPSIFT_EINVAL;
+    }
+    if (sp != LPSIFT_OK) return sp;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    if (ws_bytes < lpsift_match_workspace_size(nA, nB, n_pairs, mp)) return LPSIFT_ECAPACITY;
+    char* ws = static_cast<char*>(workspace);
+    for (int i = 0; i < n_pairs; ++i) {
+        const int st = launch_match(descA[i], nA[i], descB[i], nB[i], mp, ws, match[i], d1[i],
+                                    d2[i], static_cast<hipStream_t>(stream));
+        if (st != LPSIFT_OK) return st;
+        ws += align_up(match_workspace_bytes(nA[i], nB[i], mp), 256);
+    }
+    return LPSIFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// Multiscale window extrema (Sec. 2.2, Eq. 2) with the Eq. 1 ramp folded into
+// an exact integer key.
+//
+// One workgroup owns a T x T tile of one image, T a multiple of the largest
+// window side (about 128 px; the largest window is at most 128). The tile is
+// staged once in LDS with coalesced 4-byte loads; every pixel becomes the key
+//     value << 16 | row_in_tile << 8 | col_in_tile
+// whose unsigned order is (intensity, raster index) inside the tile, i.e. the
+// order Eq. 1 induces for any 0 < alpha < 1/(rows*cols). Level 0 windows are
+// reduced by groups of lanes (cross-lane shuffles); every larger window, which
+// the nesting condition makes a union of whole child windows, is the max / min
+// of its children's keys. Each window's extrema and integer pixel sum are
+// written to their fixed keypoint slots; nothing is compacted, so the output
+// is deterministic and no atomics are needed.
+#include "internal.h"
+
+namespace lpsift {
+namespace {
+
+struct DetectImg {
+    const uint8_t* data;
+    int64_t pitch;
+    int32_t h, w;
+    int32_t tiles_x;
+    int32_t tile_begin;        // first global tile index of this image
+    int32_t* x;
+    int32_t* y;
+    uint8_t* scale;
+    int8_t* type;
+    uint8_t* value;
+    float* contrast;
+    int64_t base[LPSIFT_MAX_SCALES];   // first slot of each scale
+};
+
+struct DetectArgs {
+    int32_t n_images;
+    int32_t n_scales;
+    int32_t T;                  // tile side
+    int32_t Tp;                 // LDS row stride of the tile (multiple of 4)
+    int32_t L[LPSIFT_MAX_SCALES];
+    int32_t lvl_off[LPSIFT_MAX_SCALES];  // LDS word offset of each level's records
+    int32_t tile_words;         // LDS word offset of the pixel tile
+    DetectImg img[kMaxBatch];
+};
+
+constexpr int kThreads = 256;
+
+__device__ inline void write_kp(const DetectImg& I, int s, int64_t slot, int ox, int oy,
+                                uint32_t key, uint32_t sum, uint32_t n, int8_t type)
+{
+    const uint32_t v = key >> 16;
+    I.x[slot] = ox + (int32_t)(key & 255u);
+    I.y[slot] = oy + (int32_t)((key >> 8) & 255u);
+    I.scale[slot] = (uint8_t)s;
+    I.type[slot] = type;
+    I.value[slot] = (uint8_t)v;
+    // |v n - sum| and 255 n are integers below 2^24: one correctly rounded division
+    const int64_t num = (int64_t)v * n - (int64_t)sum;
+    I.contrast[slot] = (float)(num < 0 ? -num : num) / (float)(255u * n);
+}
+
+__global__ __launch_bounds__(kThreads) void detect_kernel(DetectArgs args)
+{
+    extern __shared__ uint32_t smem[];
+    const int tile = blockIdx.x;
+    int im = 0;
+    for (int i = 1; i < args.n_images; ++i)
+        if (tile >= args.img[i].tile_begin) im = i;
+    const DetectImg& I = args.img[im];
+    const int T = args.T, Tp = args.Tp;
+    const int local = tile - I.tile_begin;
+    const int ty = local / I.tiles_x, tx = local - ty * I.tiles_x;
+    const int ox = tx * T, oy = ty * T;
+    const int tw = min(T, I.w - ox), th = min(T, I.h - oy);
+    uint8_t* pix = reinterpret_cast<uint8_t*>(smem + args.tile_words);
+    const int tid = threadIdx.x;
+
+    // ---- stage the tile in LDS ----
+    {
+        const uint8_t* tile0 = I.data + (int64_t)oy * I.pitch + ox;
+        const bool al4 = ((reinterpret_cast<uintptr_t>(tile0) | (uintptr_t)I.pitch) & 3u) == 0;
+        const int gpr = Tp / 4;
+        for (int idx = tid; idx < th * gpr; idx += kThreads) {
+            const int r = idx / gpr, c = (idx - r * gpr) * 4;
+            if (c >= tw) continue;
+            const uint8_t* src = tile0 + (int64_t)r * I.pitch + c;
+            uint8_t* dst = pix + r * Tp + c;
+            if (al4 && c + 4 <= tw) {
+                *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
+            } else {
+                for (int k = 0; k < 4 && c + k < tw; ++k) dst[k] = src[k];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- level 0: groups of G lanes per window ----
+    {
+        const int L0 = args.L[0];
+        const int n0 = T / L0, nw = n0 * n0;
+        int G = 1;
+        while (G < 64 && 2 * G <= L0 && 2 * G * nw <= kThreads) G *= 2;
+        const int groups = kThreads / G;
+        const int g = tid % G, grp = tid / G;
+        uint32_t* rec = smem + args.lvl_off[0];
+        const int nbx = (int)n_windows(I.w, L0);
+        for (int wb = 0; wb < nw; wb += groups) {   // uniform trip count for the shuffles
+            const int wi = wb + grp;
+            uint32_t kmax = 0u, kmin = 0xFFFFFFFFu, sum = 0u;
+            int r0 = 0, c0 = 0;
+            bool valid = false;
+            if (wi < nw) {
+                const int wy = wi / n0, wx = wi - wy * n0;
+                r0 = wy * L0;
+                c0 = wx * L0;
+                valid = r0 < th && c0 < tw;
+                const int r1 = min(r0 + L0, th), c1 = min(c0 + L0, tw);
+                for (int r = r0 + g; r < r1; r += G) {
+                    const uint8_t* row = pix + r * Tp;
+                    for (int c = c0; c < c1; ++c) {
+                        const uint32_t v = row[c];
+                        const uint32_t key = (v << 16) | ((uint32_t)r << 8) | (uint32_t)c;
+                        kmax = max(kmax, key);
+                        kmin = min(kmin, key);
+                        sum += v;
+                    }
+                }
+            }
+            for (int off = G / 2; off > 0; off >>= 1) {
+                kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+                kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
+                sum += (uint32_t)__shfl_xor((int)sum, off);
+            }
+            if (valid && g == 0) {
+                rec[3 * wi + 0] = kmax;
+                rec[3 * wi + 1] = kmin;
+                rec[3 * wi + 2] = sum;
+                const int wy = wi / n0, wx = wi - wy * n0;
+                const int64_t by = (int64_t)ty * n0 + wy, bx = (int64_t)tx * n0 + wx;
+                const int64_t slot = I.base[0] + 2 * (by * nbx + bx);
+                const uint32_t n = (uint32_t)((min(r0 + L0, th) - r0) * (min(c0 + L0, tw) - c0));
+                write_kp(I, 0, slot, ox, oy, kmax, sum, n, +1);
+                write_kp(I, 0, slot + 1, ox, oy, kmin, sum, n, -1);
+            }
+        }
+    }
+
+    // ---- larger windows: merge whole children ----
+    for (int s = 1; s < args.n_scales; ++s) {
+        __syncthreads();
+        const int Ls = args.L[s], Lc = args.L[s - 1];
+        const int ns = T / Ls, nc = T / Lc, m = Ls / Lc;
+        const uint32_t* crec = smem + args.lvl_off[s - 1];
+        uint32_t* rec = smem + args.lvl_off[s];
+        const int nbx = (int)n_windows(I.w, Ls);
+        for (int wi = tid; wi < ns * ns; wi += kThreads) {
+            const int wy = wi / ns, wx = wi - wy * ns;
+            const int r0 = wy * Ls, c0 = wx * Ls;
+            if (r0 >= th || c0 >= tw) continue;
+            uint32_t kmax = 0u, kmin = 0xFFFFFFFFu, sum = 0u;
+            for (int cy = 0; cy < m; ++cy) {
+                const int cwy = wy * m + cy;
+                if (cwy * Lc >= th) break;
+                for (int cx = 0; cx < m; ++cx) {
+                    const int cwx = wx * m + cx;
+                    if (cwx * Lc >= tw) break;
+                    const uint32_t* c = crec + 3 * (cwy * nc + cwx);
+                    kmax = max(kmax, c[0]);
+                    kmin = min(kmin, c[1]);
+                    sum += c[2];
+                }
+            }
+            rec[3 * wi + 0] = kmax;
+            rec[3 * wi + 1] = kmin;
+            rec[3 * wi + 2] = sum;
+            const int64_t by = (int64_t)ty * ns + wy, bx = (int64_t)tx * ns + wx;
+            const int64_t slot = I.base[s] + 2 * (by * nbx + bx);
+            const uint32_t n = (uint32_t)((min(r0 + Ls, th) - r0) * (min(c0 + Ls, tw) - c0));
+            write_kp(I, s, slot, ox, oy, kmax, sum, n, +1);
+            write_kp(I, s, slot + 1, ox, oy, kmin, sum, n, -1);
+        }
+    }
+}
+
+}  // namespace
+
+int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,
+                  const lpsift_keypoints* out, hipStream_t stream)
+{
+    const int Lmax = g.L[g.n_scales - 1];
+    const int T = Lmax * (Lmax < 128 ? 128 / Lmax : 1);   // ~128 px per tile side
+    DetectArgs a{};
+    a.n_scales = g.n_scales;
+    a.T = T;
+    a.Tp = (int)align_up((size_t)T, 4);
+    int words = 0;
+    for (int s = 0; s < g.n_scales; ++s) {
+        a.L[s] = g.L[s];
+        a.lvl_off[s] = words;
+        const int ns = T / g.L[s];
+        words += 3 * ns * ns;
+    }
+    a.tile_words = words;
+    const size_t lds = (size_t)words * 4 + (size_t)a.Tp * T;
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = (n - b0 < kMaxBatch) ? n - b0 : kMaxBatch;
+        a.n_images = nb;
+        int tiles = 0;
+        for (int i = 0; i < nb; ++i) {
+            const lpsift_image& im = imgs[b0 + i];
+            const lpsift_keypoints& kp = out[b0 + i];
+            DetectImg& d = a.img[i];
+            d.data = im.data;
+            d.pitch = im.pitch;
+            d.h = im.height;
+            d.w = im.width;
+            d.tiles_x = (int)n_windows(im.width, T);
+            d.tile_begin = tiles;
+            tiles += d.tiles_x * (int)n_windows(im.height, T);
+            d.x = kp.x;
+            d.y = kp.y;
+            d.scale = kp.scale;
+            d.type = kp.type;
+            d.value = kp.value;
+            d.contrast = kp.contrast;
+            int64_t base = 0;
+            for (int s = 0; s < g.n_scales; ++s) {
+                d.base[s] = base;
+                base += 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
+            }
+        }
+        hipLaunchKernelGGL(detect_kernel, dim3(tiles), dim3(kThreads), lds, stream, a);
+        if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+    }
+    return LPSIFT_OK;
+}
+
+}  // namespace lpsift

@@ -1,0 +1,85 @@
+// Internal declarations of liblpsift: launch descriptors passed by value to the
+// kernels and the host launchers each kernel file provides to the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lpsift.h"
+
+namespace lpsift {
+
+// Images per kernel launch; larger batches are split into several launches.
+constexpr int kMaxBatch = 16;
+
+__host__ __device__ inline int64_t n_windows(int64_t n, int64_t L) { return (n + L - 1) / L; }
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// floor(sqrt(v)) for v >= 0, exact for every int32 value.
+__host__ __device__ inline int isqrt_floor(int v)
+{
+    int r = (int)sqrtf((float)v);
+    while (r > 0 && r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+// Number of integer offsets (dx, dy) with dx^2 + dy^2 <= r2 (r2 >= 0).
+__host__ __device__ inline int disc_count(int r2)
+{
+    const int R = isqrt_floor(r2);
+    int n = 0;
+    for (int dy = -R; dy <= R; ++dy) n += 2 * isqrt_floor(r2 - dy * dy) + 1;
+    return n;
+}
+
+// Per-scale geometry of orientation and description (Eq. 3).
+struct ScaleGeom {
+    float ws;          // subregion side w_s = beta L
+    float inv_ws;      // 1 / w_s
+    float k_orient;    // -log2(e) / (2 sigma_o^2), sigma_o = w_s / 2
+    float k_desc;      // -log2(e) / (2 (d/2)^2 w_s^2), Gaussian of sigma d/2 cells
+    int r2_orient;     // round(1.5 w_s)^2
+    int r2_desc;       // floor((w_s sqrt(2) (d+1)/2)^2)
+    int off_orient;    // entry offset of the orientation disc table
+    int n_orient;      // entries of that table
+    int off_desc;      // entry offset of the descriptor disc table
+    int n_desc;
+};
+
+struct Geometry {
+    int n_scales;
+    int L[LPSIFT_MAX_SCALES];
+    ScaleGeom s[LPSIFT_MAX_SCALES];
+    int table_entries;  // total int32 entries of all disc tables
+};
+
+// Validated, derived view of lpsift_params. Returns LPSIFT_OK or an error.
+int make_geometry(const lpsift_params* p, Geometry* g);
+
+// ---- launchers (enqueue only; return LPSIFT_OK or LPSIFT_EHIP) ----
+
+int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,
+                  const lpsift_keypoints* out, hipStream_t s);
+
+// Workspace layout of describe: disc tables, then one float2 gradient field
+// per image (8 bytes per pixel), each 256-byte aligned.
+size_t describe_workspace_bytes(const lpsift_image* imgs, int n, const Geometry& g);
+int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
+                    const Geometry& g, void* ws, float* const* theta, float* const* desc,
+                    hipStream_t s);
+
+struct MatchPlan {
+    int chunks;          // candidate-range split
+    int64_t chunk_len;   // candidates per chunk, a multiple of 32
+};
+MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp);
+size_t match_workspace_bytes(int64_t nA, int64_t nB, const lpsift_match_params* mp);
+int launch_match(const float* A, int64_t nA, const float* B, int64_t nB,
+                 const lpsift_match_params* mp, void* ws, int32_t* match, float* d1,
+                 float* d2, hipStream_t s);
+
+}  // namespace lpsift

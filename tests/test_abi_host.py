@@ -1,0 +1,153 @@
+"""The C-ABI library on the host: it loads without a GPU, exports every
+function include/lpsift.h declares, and rejects bad arguments with a status
+code before any GPU call (no pointer passed here is ever dereferenced)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2405_08578_amd as lp
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000          # a non-null "device" address that validation never touches
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lp.LIB_PATH):
+        from paper_2405_08578_amd import build
+        build.build()
+    return lp.load()
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "lpsift.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lpsift_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lp.EXPORTS)
+
+
+def test_version_and_status_strings(lib):
+    assert lib.lpsift_version() >= 100
+    for st in (0, -1, -2, -3, -4):
+        assert lp.status_string(st) != "unknown status"
+    assert lp.status_string(7) == "unknown status"
+
+
+@pytest.mark.parametrize("h,w,Ls", [(480, 640, [16, 32, 64]), (1600, 2600, [16, 32, 64, 128]),
+                                    (1, 1, [4]), (33, 97, [4, 8, 24])])
+def test_num_keypoints_matches_oracle(lib, h, w, Ls):
+    assert lp.num_keypoints(h, w, lp.Params(Ls)) == oracle.num_keypoints(h, w, Ls)
+
+
+def test_num_keypoints_rejects(lib):
+    p = lp.Params([16])
+    assert lib.lpsift_num_keypoints(0, 10, ctypes.byref(p.c())) == -1
+    assert lib.lpsift_num_keypoints(10, 10, None) == -1
+
+
+def image(h=64, w=64, pitch=None):
+    im = lp.lpsift_image()
+    im.data, im.height, im.width = FAKE, h, w
+    im.pitch = w if pitch is None else pitch
+    return im
+
+
+def kps(n):
+    k = lp.lpsift_keypoints()
+    for f in ("x", "y", "scale", "type", "value", "contrast"):
+        setattr(k, f, FAKE)
+    k.capacity = n
+    return k
+
+
+def detect(lib, params, ims, ks):
+    a = (lp.lpsift_image * len(ims))(*ims)
+    b = (lp.lpsift_keypoints * len(ks))(*ks)
+    return lib.lpsift_detect(a, len(ims), ctypes.byref(params), b, None)
+
+
+def test_detect_validation(lib):
+    P = lp.Params([16, 32]).c()
+    n = lp.num_keypoints(64, 64, lp.Params([16, 32]))
+    assert detect(lib, P, [image(pitch=10)], [kps(n)]) == lp.LPSIFT_EINVAL
+    assert detect(lib, P, [image(h=0)], [kps(n)]) == lp.LPSIFT_EINVAL
+    assert detect(lib, P, [image()], [kps(n - 1)]) == lp.LPSIFT_ECAPACITY
+    k = kps(n)
+    k.contrast = None
+    assert detect(lib, P, [image()], [k]) == lp.LPSIFT_EINVAL
+    im = image()
+    im.data = None
+    assert detect(lib, P, [im], [kps(n)]) == lp.LPSIFT_EINVAL
+    bad = lp.Params([32, 16]).c()                       # not ascending
+    assert detect(lib, bad, [image()], [kps(10**6)]) == lp.LPSIFT_EINVAL
+    small = lp.Params([2, 16]).c()                      # L below 4
+    assert detect(lib, small, [image()], [kps(10**6)]) == lp.LPSIFT_EINVAL
+    nonnested = lp.Params([32, 40]).c()                 # valid method, not on the GPU
+    assert detect(lib, nonnested, [image()], [kps(10**6)]) == lp.LPSIFT_EUNSUPPORTED
+    big = lp.Params([256, 512]).c()
+    assert detect(lib, big, [image()], [kps(10**6)]) == lp.LPSIFT_EUNSUPPORTED
+    d8 = lp.Params([16, 32], d=8).c()
+    assert detect(lib, d8, [image()], [kps(10**6)]) == lp.LPSIFT_EUNSUPPORTED
+    zero = lp.lpsift_params()
+    assert detect(lib, zero, [image()], [kps(n)]) == lp.LPSIFT_EINVAL
+    a = (lp.lpsift_image * 1)(image())
+    assert lib.lpsift_detect(a, 0, ctypes.byref(P), (lp.lpsift_keypoints * 1)(kps(n)), None) \
+        == lp.LPSIFT_EINVAL
+
+
+def test_describe_validation_and_workspace(lib):
+    prm = lp.Params([16, 32, 64, 128])
+    P = prm.c()
+    ims = (lp.lpsift_image * 2)(image(1600, 2600), image(480, 640))
+    need = lib.lpsift_describe_workspace_size(ims, 2, ctypes.byref(P))
+    # the two gradient fields (8 bytes per pixel) dominate
+    assert need >= 8 * (1600 * 2600 + 480 * 640)
+    assert need < 8 * (1600 * 2600 + 480 * 640) + (1 << 20)
+    n0 = lp.num_keypoints(1600, 2600, prm)
+    n1 = lp.num_keypoints(480, 640, prm)
+    ks = (lp.lpsift_keypoints * 2)(kps(n0), kps(n1))
+    th = (ctypes.c_void_p * 2)(FAKE, FAKE)
+    de = (ctypes.c_void_p * 2)(FAKE, FAKE)
+    ws = 0x100000
+    call = lambda wsb, k=ks, t=th: lib.lpsift_describe(ims, 2, k, ctypes.byref(P), ws, wsb, t, de, None)
+    assert call(need - 1) == lp.LPSIFT_ECAPACITY
+    ks2 = (lp.lpsift_keypoints * 2)(kps(n0), kps(n1 - 1))
+    assert call(need, k=ks2) == lp.LPSIFT_ECAPACITY
+    th2 = (ctypes.c_void_p * 2)(FAKE, None)
+    assert call(need, t=th2) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_describe(ims, 2, ks, ctypes.byref(P), ws + 4, need, th, de, None) \
+        == lp.LPSIFT_EINVAL                              # workspace not 256-byte aligned
+
+
+def test_match_validation_and_workspace(lib):
+    mp = lp.match_params()
+    nA, nB = [43396], [43396]
+    need = lp.match_workspace_size(nA, nB, mp)
+    assert need >= 4 * 43396
+    arr = lambda *v: (ctypes.c_void_p * len(v))(*v)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+
+    def call(mp_, nA_=43396, nB_=43396, ws=0x100000, wsb=need, dA=FAKE):
+        return lib.lpsift_match(arr(dA), i64(nA_), arr(FAKE), i64(nB_), 1, ctypes.byref(mp_), ws,
+                                wsb, arr(FAKE), arr(FAKE), arr(FAKE), None)
+    assert call(mp, wsb=need - 1) == lp.LPSIFT_ECAPACITY
+    assert call(mp, nA_=-1) == lp.LPSIFT_EINVAL
+    assert call(mp, dA=FAKE + 4) == lp.LPSIFT_EINVAL         # not 16-byte aligned
+    assert call(mp, ws=0x100000 + 8) == lp.LPSIFT_EINVAL
+    for bad in (lp.match_params(ratio=0.0), lp.match_params(ratio=math.nan),
+                lp.match_params(abs_thresh=math.nan), lp.match_params(abs_thresh=-1.0),
+                lp.match_params(b_chunks=17), lp.match_params(precision=3)):
+        assert call(bad) == lp.LPSIFT_EINVAL
+    assert call(lp.match_params(precision=1)) == lp.LPSIFT_EUNSUPPORTED
+    assert lp.match_workspace_size([10], [0], mp) >= 0

@@ -1,0 +1,119 @@
+"""GPU parity of lpsift_describe against the FP64 oracle.
+
+Tolerance: descriptors within 1e-4 relative L2 of the FP64 oracle and
+orientations within 1e-4 rad, except keypoints whose oracle orientation
+histogram has a non-adjacent near-tie (relative gap < 1e-5), where the argmax
+may legitimately differ between FP32 and FP64; those are counted and must stay
+rare.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2405_08578_amd as lp
+from gpu_util import (angle_diff, kp_numpy, oracle_features_at, orientation_ambiguity, rel_l2,
+                      say, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+DESC_TOL = 1e-4
+THETA_TOL = 1e-4
+AMBIG = 1e-5
+
+
+def check(img, kpn, theta, desc, Ls, idx=None, max_ambiguous=0.001):
+    th_o, d_o, hist = oracle_features_at(img, kpn, Ls, idx)
+    if idx is not None:
+        theta, desc = theta[idx], desc[idx]
+    amb = orientation_ambiguity(hist) < AMBIG
+    ok = ~amb
+    err = rel_l2(desc.astype(np.float64), d_o)
+    dth = angle_diff(theta.astype(np.float64), th_o)
+    assert amb.mean() <= max_ambiguous, f"{amb.sum()} ambiguous orientations"
+    assert np.all(dth[ok] < THETA_TOL), f"theta max err {dth[ok].max()}"
+    assert np.all(err[ok] < DESC_TOL), f"desc max rel err {err[ok].max()}"
+    return err[ok].max() if ok.any() else 0.0
+
+
+def texture(h, w, seed, n_blobs):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cv = synth.render_texture(0, 0, w, h, n_blobs, rng)
+    return synth.to_uint8(cv.tex, rng)
+
+
+@pytest.mark.parametrize("h,w,Ls,seed", [
+    (40, 50, [4, 8, 16], 0),          # supports clipped by every border
+    (129, 200, [16, 32, 64, 128], 1),
+    (300, 257, [8, 16, 32], 2),
+    (96, 96, [16, 48], 3),
+])
+def test_describe_small_images(gpu, h, w, Ls, seed):
+    img = texture(h, w, seed, max(4, h * w // 500))
+    say("describe", h, w, Ls, seed)
+    P = lp.Params(Ls)
+    kps, th, de = lp.features([to_dev(img, gpu)], P)
+    kpn = kp_numpy(kps[0])
+    check(img, kpn, th[0].cpu().numpy(), de[0].cpu().numpy(), Ls, max_ambiguous=0.02)
+
+
+def test_describe_config0_all_keypoints(gpu):
+    pair = synth.config_pair(0)
+    Ls = [16, 32, 64]
+    say("describe config 0 pair")
+    P = lp.Params(Ls)
+    kps, th, de = lp.features([to_dev(pair.A, gpu), to_dev(pair.B, gpu)], P)
+    for img, kp, t, d in zip((pair.A, pair.B), kps, th, de):
+        check(img, kp_numpy(kp), t.cpu().numpy(), d.cpu().numpy(), Ls)
+
+
+def test_describe_config1_sampled(gpu):
+    pair = synth.config_pair(1)
+    Ls = [16, 32, 64, 128]
+    say("describe config 1 pair, sampled")
+    P = lp.Params(Ls)
+    kps, th, de = lp.features([to_dev(pair.A, gpu), to_dev(pair.B, gpu)], P)
+    rng = np.random.default_rng(1)
+    for img, kp, t, d in zip((pair.A, pair.B), kps, th, de):
+        kpn = kp_numpy(kp)
+        n = len(kpn["x"])
+        # every slot of the largest scale plus a random sample of the rest
+        idx = np.unique(np.r_[np.nonzero(kpn["scale"] == 3)[0], rng.choice(n, 3000, replace=False)])
+        check(img, kpn, t.cpu().numpy(), d.cpu().numpy(), Ls, idx=idx)
+
+
+def test_describe_properties_and_determinism(gpu):
+    pair = synth.config_pair(0)
+    P = lp.Params([16, 32, 64])
+    t = to_dev(pair.A, gpu)
+    kps = lp.detect([t], P)
+    th1, d1 = lp.describe([t], kps, P)
+    th2, d2 = lp.describe([t], kps, P)
+    a, b = d1[0].cpu().numpy(), d2[0].cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(th1[0].cpu().numpy(), th2[0].cpu().numpy())
+    nrm = np.linalg.norm(a.astype(np.float64), axis=1)
+    assert np.all((np.abs(nrm - 1) < 1e-5) | (nrm == 0))
+    assert a.min() >= 0
+
+
+def test_describe_flat_image(gpu):
+    img = np.full((64, 80), 200, np.uint8)
+    P = lp.Params([16, 32])
+    kps, th, de = lp.features([to_dev(img, gpu)], P)
+    assert np.all(th[0].cpu().numpy() == 0) and np.all(de[0].cpu().numpy() == 0)
+
+
+def test_describe_ramp_closed_form(gpu):
+    # constant gradient: orientation exactly 0 and all mass in direction bin 0
+    yy, xx = np.mgrid[0:96, 0:96]
+    img = (80 + xx).astype(np.uint8)
+    P = lp.Params([16, 32])
+    kps, th, de = lp.features([to_dev(img, gpu)], P)
+    kpn = kp_numpy(kps[0])
+    inner = (kpn["x"] > 30) & (kpn["x"] < 65) & (kpn["y"] > 30) & (kpn["y"] < 65)
+    assert inner.any()
+    assert np.all(np.abs(th[0].cpu().numpy()[inner]) < 1e-6)
+    d = de[0].cpu().numpy()[inner].reshape(-1, 16, 8)
+    assert np.all(d[:, :, 1:] < 1e-6)

@@ -1,0 +1,148 @@
+"""GPU parity of lpsift_match against the FP64 oracle matcher.
+
+Rules:
+ (i)  the oracle matcher run in FP64 on the GPU's own descriptors gives the same
+      list (match index or -1) for every query at least 1e-6 (relative) away
+      from a decision boundary (ratio test, nearest-neighbour tie), and the
+      GPU's FP32 d1, d2 agree with the FP64 distances to 1e-5 relative;
+ (ii) the oracle end to end (FP64 descriptors) and the GPU end to end give the
+      same list outside a 1e-3 band around those boundaries.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2405_08578_amd as lp
+from gpu_util import kp_numpy, match_margins, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def run_match(gpu, A, B, **kw):
+    import torch
+    ta = torch.from_numpy(np.ascontiguousarray(A, np.float32)).to(gpu)
+    tb = torch.from_numpy(np.ascontiguousarray(B, np.float32)).to(gpu)
+    r = lp.match([ta], [tb], **kw)[0]
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def check_rule_i(A32, B32, g, ratio=0.8, band=1e-6):
+    o = oracle.match(A32.astype(np.float64), B32.astype(np.float64), ratio=ratio)
+    marg = match_margins(o["d1"], o["d2"], ratio)
+    safe = marg > band
+    assert np.array_equal(g["match"][safe], o["match"][safe]), \
+        f"{np.sum(g['match'][safe] != o['match'][safe])} differing lists"
+    fin = np.isfinite(o["d2"])
+    assert np.allclose(g["d1"], o["d1"], rtol=1e-5, atol=1e-6)
+    assert np.allclose(g["d2"][fin], o["d2"][fin], rtol=1e-5, atol=1e-6)
+    assert np.all(np.isinf(g["d2"][~fin]))
+    return int((~safe).sum())
+
+
+@pytest.mark.parametrize("nA,nB,seed", [(1, 1, 0), (5, 3, 1), (300, 31, 2), (300, 33, 3),
+                                        (257, 1000, 4), (1000, 257, 5), (4099, 5003, 6),
+                                        (256, 64, 7)])
+@pytest.mark.parametrize("chunks", [0, 1, 3])
+def test_match_random_sets(gpu, nA, nB, seed, chunks):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = synth.random_unit_rows(nB, 128, rng).astype(np.float32)
+    A = synth.noisy_copies(B.astype(np.float64), rng.integers(0, nB, nA), 0.08, rng).astype(np.float32)
+    say("match", nA, nB, seed, chunks)
+    g = run_match(gpu, A, B, b_chunks=chunks)
+    check_rule_i(A, B, g)
+
+
+def test_match_exact_cases(gpu):
+    A = np.zeros((3, 128), np.float32)
+    A[1, 0] = 1.0
+    A[2, 1] = 1.0
+    B = np.zeros((3, 128), np.float32)
+    B[0, 0] = 4.0              # query 0: d1 = 4 ...
+    B[1, 1] = 5.0              # ... d2 = 5, rejected since 0.8 * 5 == 4.0
+    B[2, 2] = 7.0
+    say("match exact")
+    g = run_match(gpu, A, B)
+    assert (g["d1"][0], g["d2"][0], g["match"][0]) == (4.0, 5.0, -1)
+    B2 = B.copy()
+    B2[1, 1] = 5.000001
+    assert run_match(gpu, A, B2)["match"][0] == 0
+    # identical candidates: a d1 == d2 tie is rejected, index of the first kept
+    B3 = np.zeros((4, 128), np.float32)
+    B3[1, 0] = 1.0
+    B3[3, 0] = 1.0
+    B3[0, 5] = 1.0
+    g = run_match(gpu, A, B3)
+    assert g["match"][1] == -1 and g["d1"][1] == 0.0 and g["d2"][1] == 0.0
+
+
+def test_match_degenerate_sizes(gpu):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(3))
+    A = synth.random_unit_rows(7, 128, rng).astype(np.float32)
+    g = run_match(gpu, A, A[:1])
+    assert np.all(g["match"] == 0) and np.all(np.isinf(g["d2"]))
+    ta = torch.from_numpy(A).to(gpu)
+    empty = torch.zeros((0, 128), dtype=torch.float32, device=gpu)
+    r = lp.match([ta], [empty])[0]
+    assert np.all(r["match"].cpu().numpy() == -1)
+    r = lp.match([empty], [ta])[0]
+    assert r["match"].numel() == 0
+
+
+def test_match_abs_threshold(gpu):
+    rng = np.random.Generator(np.random.PCG64(9))
+    B = synth.random_unit_rows(500, 128, rng).astype(np.float32)
+    A = synth.noisy_copies(B.astype(np.float64), rng.integers(0, 500, 400), 0.1, rng).astype(np.float32)
+    g = run_match(gpu, A, B, ratio=1.0, abs_thresh=0.3)
+    o = oracle.match(A.astype(np.float64), B.astype(np.float64), ratio=1.0, abs_thresh=0.3)
+    safe = (np.abs(o["d1"] - 0.3) > 1e-5) & (match_margins(o["d1"], o["d2"], 1.0) > 1e-6)
+    assert np.array_equal(g["match"][safe], o["match"][safe])
+
+
+def features_gpu(gpu, imgs, Ls):
+    P = lp.Params(Ls)
+    kps, th, de = lp.features([to_dev(i, gpu) for i in imgs], P)
+    return kps, de
+
+
+def test_match_config0_end_to_end(gpu):
+    pair = synth.config_pair(0)
+    Ls = [16, 32, 64]
+    say("match config 0 end to end")
+    kps, de = features_gpu(gpu, (pair.A, pair.B), Ls)
+    r = lp.match([de[0]], [de[1]])[0]
+    g = {k: v.cpu().numpy() for k, v in r.items()}
+    A32, B32 = de[0].cpu().numpy(), de[1].cpu().numpy()
+    check_rule_i(A32, B32, g)
+    # (ii) oracle end to end
+    _, _, dA = oracle.features(pair.A, Ls)
+    _, _, dB = oracle.features(pair.B, Ls)
+    o = oracle.match(dA, dB)
+    safe = match_margins(o["d1"], o["d2"], 0.8) > 1e-3
+    assert np.array_equal(g["match"][safe], o["match"][safe])
+    assert (~safe).sum() < 0.05 * len(safe)
+    assert (g["match"] >= 0).sum() > 50
+
+
+def test_match_config1_sampled_queries(gpu):
+    pair = synth.config_pair(1)
+    say("match config 1 pair, sampled queries")
+    kps, de = features_gpu(gpu, (pair.A, pair.B), [16, 32, 64, 128])
+    r = lp.match([de[0]], [de[1]])[0]
+    g = {k: v.cpu().numpy() for k, v in r.items()}
+    A32, B32 = de[0].cpu().numpy(), de[1].cpu().numpy()
+    idx = np.random.default_rng(0).choice(len(A32), 768, replace=False)
+    check_rule_i(A32[idx], B32, {k: v[idx] for k, v in g.items()})
+
+
+def test_match_deterministic(gpu):
+    rng = np.random.Generator(np.random.PCG64(21))
+    B = synth.random_unit_rows(3000, 128, rng).astype(np.float32)
+    A = synth.noisy_copies(B.astype(np.float64), rng.integers(0, 3000, 2000), 0.1, rng).astype(np.float32)
+    g1 = run_match(gpu, A, B)
+    g2 = run_match(gpu, A, B)
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k])
