@@ -10,15 +10,19 @@
 //     (magnitude, angle in turns in [0, 1)); border pixels get magnitude 0.
 //     Each image pixel is visited by ~10 keypoint supports, so the atan2 and
 //     the square root are paid once per pixel instead of once per visit.
-//  3. orient_describe_kernel: one wavefront per keypoint. Lane l walks the
-//     l-th contiguous 1/64 of the disc table, so the 64 lanes of one step are
-//     spread over the whole support and their votes land in different cells;
-//     votes go to a per-wave histogram in LDS with ds_add_f32. The histogram
-//     is private to the wave, so its accumulation order is fixed by the
-//     instruction stream. Orientation (36 bins, smoothing, argmax, parabola),
-//     then the 128-bin descriptor, normalisation, clipping at 0.2 and
-//     renormalisation happen in the same wave; the descriptor row is stored
-//     with two coalesced 256-byte writes.
+//  3. orient_describe_kernel: one wavefront per keypoint, four per workgroup.
+//     Lane l walks the l-th contiguous 1/64 of the disc table, four visits at a
+//     time with all their loads issued before any is used. Votes are
+//     accumulated in LDS as 64-bit fixed point with integer atomics:
+//     ds_add_u64 runs at close to full rate where ds_add_f32 does not, and
+//     integer sums do not depend on the order of the votes, so the result is
+//     bit-identical from run to run. The scale 2^(62 - b), with 2^b above
+//     (visits x 361) >= the total vote mass (|gradient| <= 255 sqrt 2, all
+//     interpolation weights <= 1), makes overflow impossible while resolving
+//     votes to ~2^-40 of the total. Orientation (36 bins, smoothing, argmax,
+//     parabola), then the 128-bin descriptor, normalisation, clipping at 0.2
+//     and renormalisation happen in the same wave; the descriptor row is
+//     stored with two coalesced 256-byte writes.
 #include "internal.h"
 
 namespace lpsift {
@@ -42,18 +46,38 @@ __device__ inline int32_t pack_offset(int dx, int dy)
     return (int32_t)((uint32_t)(dx & 0xFFFF) | ((uint32_t)dy << 16));
 }
 
-// One workgroup per table; thread t writes rows dy = -R + t, -R + t + 256, ...
-__global__ __launch_bounds__(256) void disc_tables_kernel(TableArgs a, int32_t* tables)
+constexpr int kTabThreads = 256;
+
+// One workgroup per table. Thread t owns a contiguous run of rows; a block
+// scan of the per-thread entry counts gives every row its start.
+__global__ __launch_bounds__(kTabThreads) void disc_tables_kernel(TableArgs a, int32_t* tables)
 {
-    const int t = blockIdx.x;
+    __shared__ int scan[kTabThreads];
+    const int t = blockIdx.x, tid = threadIdx.x;
     const int r2 = a.r2[t];
     const int R = isqrt_floor(r2);
+    const int rows = 2 * R + 1;
+    const int per = (rows + kTabThreads - 1) / kTabThreads;
+    const int row0 = tid * per;
+    int cnt = 0;
+    for (int i = row0; i < row0 + per && i < rows; ++i) {
+        const int dy = i - R;
+        cnt += 2 * isqrt_floor(r2 - dy * dy) + 1;
+    }
+    scan[tid] = cnt;
+    __syncthreads();
+    for (int off = 1; off < kTabThreads; off <<= 1) {   // inclusive Hillis-Steele scan
+        const int v = (tid >= off) ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    int start = scan[tid] - cnt;
     int32_t* out = tables + a.off[t];
-    for (int dy = -R + (int)threadIdx.x; dy <= R; dy += blockDim.x) {
-        int start = 0;
-        for (int y = -R; y < dy; ++y) start += 2 * isqrt_floor(r2 - y * y) + 1;
+    for (int i = row0; i < row0 + per && i < rows; ++i) {
+        const int dy = i - R;
         const int hw = isqrt_floor(r2 - dy * dy);
-        for (int dx = -hw; dx <= hw; ++dx) out[start + dx + hw] = pack_offset(dx, dy);
+        for (int dx = -hw; dx <= hw; ++dx) out[start++] = pack_offset(dx, dy);
     }
 }
 
@@ -71,12 +95,12 @@ struct FieldArgs {
     FieldImg img[kDescBatch];
 };
 
-// grid: (ceil(w/64), h, image); block 64 lanes along a row.
-__global__ __launch_bounds__(64) void polar_field_kernel(FieldArgs a)
+// grid: (ceil(w/256), h, image); one row segment of 256 pixels per workgroup.
+__global__ __launch_bounds__(256) void polar_field_kernel(FieldArgs a)
 {
     const FieldImg& I = a.img[blockIdx.z];
     const int r = blockIdx.y;
-    const int c = blockIdx.x * 64 + threadIdx.x;
+    const int c = blockIdx.x * 256 + threadIdx.x;
     if (r >= I.h || c >= I.w) return;
     float2 out = make_float2(0.0f, 0.0f);
     if (r >= 1 && r <= I.h - 2 && c >= 1 && c <= I.w - 2) {
@@ -108,6 +132,7 @@ struct DescImg {
 struct DescArgs {   // passed by value: keep well under 4 KB
     int32_t n_images;
     int32_t n_scales;
+    int64_t n_items;
     ScaleGeom geom[LPSIFT_MAX_SCALES];
     // Work is ordered by scale, largest first, so the longest waves start first.
     // Scale s (in that order) covers work items [scale_begin[s], scale_begin[s+1]).
@@ -120,6 +145,10 @@ struct DescArgs {   // passed by value: keep well under 4 KB
     DescImg img[kDescBatch];
 };
 
+constexpr int kWaves = 4;          // keypoints per workgroup
+constexpr int kUnroll = 4;         // visits per lane per step
+constexpr int kBins = 128 + 36;    // descriptor bins, then orientation bins
+
 __device__ inline float wave_sum(float v)
 {
 #pragma unroll
@@ -127,11 +156,27 @@ __device__ inline float wave_sum(float v)
     return v;
 }
 
-__global__ __launch_bounds__(64) void orient_describe_kernel(DescArgs a, const int32_t* tables)
+// Fixed-point scale for at most `visits` votes of total mass <= visits * 361.
+__device__ inline float fixed_scale(int visits)
 {
-    __shared__ float hist[128 + 36];
-    const int lane = threadIdx.x;
-    const int64_t item = blockIdx.x;
+    const uint64_t bound = (uint64_t)visits * 361u + 1u;
+    const int bits = 64 - __clzll((long long)bound);
+    return exp2f((float)(62 - bits));
+}
+
+__device__ inline void vote(unsigned long long* h, float w, float scale)
+{
+    atomicAdd(h, (unsigned long long)(w * scale));
+}
+
+__global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const int32_t* tables)
+{
+    __shared__ unsigned long long hist_all[kWaves][kBins];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t item_raw = (int64_t)blockIdx.x * kWaves + wave;
+    const bool live = item_raw < a.n_items;
+    const int64_t item = live ? item_raw : 0;
+    unsigned long long* hist = hist_all[wave];
 
     // locate (scale, image, slot) of this work item
     int so = 0;
@@ -145,51 +190,67 @@ __global__ __launch_bounds__(64) void orient_describe_kernel(DescArgs a, const i
     const float2* field = I.field;
     const int W = I.w, H = I.h;
 
-    // ---- orientation histogram ----
-    float* ho = hist + 128;
-    if (lane < 36) ho[lane] = 0.0f;
+    for (int b = lane; b < kBins; b += 64) hist[b] = 0ull;
     __syncthreads();
-    {
-        const int n = G.n_orient;
-        const int per = (n + 63) / 64;
-        const int32_t* tab = tables + G.off_orient;
-        for (int it = 0; it < per; ++it) {
-            const int j = lane * per + it;
-            if (j >= n) break;
-            const int32_t e = tab[j];
-            const int dx = (int)(int16_t)(e & 0xFFFF), dy = e >> 16;
-            const int px = kx + dx, py = ky + dy;
-            if (px < 0 || px >= W || py < 0 || py >= H) continue;
-            const float2 ft = field[(int64_t)py * W + px];
-            if (ft.x == 0.0f) continue;
-            const float wt = ft.x * exp2f((float)(dx * dx + dy * dy) * G.k_orient);
-            const float t = ft.y * 36.0f;
+
+    // ---- orientation histogram: 36 bins ----
+    unsigned long long* ho = hist + 128;
+    const int n = live ? G.n_orient : 0;
+    const int per = (n + 63) / 64;
+    const float scale = fixed_scale(n);
+    const int32_t* tab = tables + G.off_orient;
+    for (int it0 = 0; it0 < per; it0 += kUnroll) {
+        int dx[kUnroll], dy[kUnroll];
+        bool ok[kUnroll];
+        float2 ft[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = lane * per + it0 + u;
+            ok[u] = (it0 + u < per) && j < n;
+            const int32_t e = ok[u] ? tab[j] : 0;
+            dx[u] = (int)(int16_t)(e & 0xFFFF);
+            dy[u] = e >> 16;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int px = kx + dx[u], py = ky + dy[u];
+            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
+            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (ft[u].x == 0.0f) continue;
+            const float wt = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
+            const float t = ft[u].y * 36.0f;
             const float k0f = floorf(t);
             const float fr = t - k0f;
             int k0 = (int)k0f;
             if (k0 >= 36) k0 -= 36;
             const int k1 = (k0 == 35) ? 0 : k0 + 1;
-            atomicAdd(&ho[k0], (1.0f - fr) * wt);
-            atomicAdd(&ho[k1], fr * wt);
+            vote(ho + k0, (1.0f - fr) * wt, scale);
+            vote(ho + k1, fr * wt, scale);
         }
     }
     __syncthreads();
 
     // smoothing, argmax (lowest bin on ties), parabolic refinement
+    const float inv = 1.0f / scale;
     float sm = -1.0f;
     if (lane < 36) {
-        sm = (ho[(lane + 34) % 36] + 4.0f * ho[(lane + 35) % 36] + 6.0f * ho[lane]
-              + 4.0f * ho[(lane + 1) % 36] + ho[(lane + 2) % 36]) / 16.0f;
+        const float h2m = (float)ho[(lane + 34) % 36] * inv, h1m = (float)ho[(lane + 35) % 36] * inv;
+        const float h0 = (float)ho[lane] * inv;
+        const float h1p = (float)ho[(lane + 1) % 36] * inv, h2p = (float)ho[(lane + 2) % 36] * inv;
+        sm = (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f;
     }
     float bv = sm;
     int bk = lane;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const float ov = __shfl_xor(bv, off);
-        const int ok = __shfl_xor(bk, off);
-        if (ov > bv || (ov == bv && ok < bk)) {
+        const int okk = __shfl_xor(bk, off);
+        if (ov > bv || (ov == bv && okk < bk)) {
             bv = ov;
-            bk = ok;
+            bk = okk;
         }
     }
     const float hm = __shfl(sm, (bk + 35) % 36);
@@ -197,34 +258,44 @@ __global__ __launch_bounds__(64) void orient_describe_kernel(DescArgs a, const i
     const float den = hm - 2.0f * bv + hp;
     const float offp = (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
     const float th_turns = ((float)bk + offp) / 36.0f;
-    if (lane == 0) I.theta[slot] = th_turns * 6.283185307179586f;
+    if (live && lane == 0) I.theta[slot] = th_turns * 6.283185307179586f;
 
-    // ---- descriptor histogram ----
-    hist[lane] = 0.0f;
-    hist[lane + 64] = 0.0f;
-    __syncthreads();
-    {
-        float sn, cs;
-        sincospif(2.0f * th_turns, &sn, &cs);
-        const float iw = G.inv_ws;
-        const int n = G.n_desc;
-        const int per = (n + 63) / 64;
-        const int32_t* tab = tables + G.off_desc;
-        for (int it = 0; it < per; ++it) {
-            const int j = lane * per + it;
-            if (j >= n) break;
-            const int32_t e = tab[j];
-            const int dx = (int)(int16_t)(e & 0xFFFF), dy = e >> 16;
-            const int px = kx + dx, py = ky + dy;
-            if (px < 0 || px >= W || py < 0 || py >= H) continue;
-            const float2 ft = field[(int64_t)py * W + px];
-            if (ft.x == 0.0f) continue;
+    // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
+    float sn, cs;
+    sincospif(2.0f * th_turns, &sn, &cs);
+    const float iw = G.inv_ws;
+    const int nd = live ? G.n_desc : 0;
+    const int perd = (nd + 63) / 64;
+    const float dscale = fixed_scale(nd);
+    const int32_t* tabd = tables + G.off_desc;
+    for (int it0 = 0; it0 < perd; it0 += kUnroll) {
+        int dx[kUnroll], dy[kUnroll];
+        bool ok[kUnroll];
+        float2 ft[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = lane * perd + it0 + u;
+            ok[u] = (it0 + u < perd) && j < nd;
+            const int32_t e = ok[u] ? tabd[j] : 0;
+            dx[u] = (int)(int16_t)(e & 0xFFFF);
+            dy[u] = e >> 16;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int px = kx + dx[u], py = ky + dy[u];
+            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
+            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (ft[u].x == 0.0f) continue;
             // offset rotated by -theta0, in subregion units
-            const float u = (cs * (float)dx + sn * (float)dy) * iw;
-            const float v = (cs * (float)dy - sn * (float)dx) * iw;
-            if (fabsf(u) >= 2.5f || fabsf(v) >= 2.5f) continue;   // no cell reachable
-            const float m = ft.x * exp2f((float)(dx * dx + dy * dy) * G.k_desc);
-            float rel = ft.y - th_turns;
+            const float fdx = (float)dx[u], fdy = (float)dy[u];
+            const float uu = (cs * fdx + sn * fdy) * iw;
+            const float vv = (cs * fdy - sn * fdx) * iw;
+            if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
+            const float m = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
+            float rel = ft[u].y - th_turns;
             rel -= floorf(rel);
             const float t = rel * 8.0f;
             const float o0f = floorf(t);
@@ -232,7 +303,7 @@ __global__ __launch_bounds__(64) void orient_describe_kernel(DescArgs a, const i
             int o0 = (int)o0f;
             if (o0 >= 8) o0 -= 8;
             const int o1 = (o0 + 1) & 7;
-            const float cu = u + 1.5f, cv = v + 1.5f;
+            const float cu = uu + 1.5f, cv = vv + 1.5f;
             const float ix0f = floorf(cu), iy0f = floorf(cv);
             const float fx = cu - ix0f, fy = cv - iy0f;
             const int ix0 = (int)ix0f, iy0 = (int)iy0f;
@@ -246,9 +317,9 @@ __global__ __launch_bounds__(64) void orient_describe_kernel(DescArgs a, const i
                     const int ix = ix0 + jx;
                     if (ix < 0 || ix > 3) continue;
                     const float wxy = m * (jx ? fx : 1.0f - fx) * wy;
-                    float* cell = hist + (iy * 4 + ix) * 8;
-                    atomicAdd(cell + o0, wxy * (1.0f - fo));
-                    atomicAdd(cell + o1, wxy * fo);
+                    unsigned long long* cell = hist + (iy * 4 + ix) * 8;
+                    vote(cell + o0, wxy * (1.0f - fo), dscale);
+                    vote(cell + o1, wxy * fo, dscale);
                 }
             }
         }
@@ -256,14 +327,17 @@ __global__ __launch_bounds__(64) void orient_describe_kernel(DescArgs a, const i
     __syncthreads();
 
     // normalise, clip at 0.2, normalise again
-    float d0 = hist[lane], d1 = hist[lane + 64];
+    const float dinv = 1.0f / dscale;
+    float d0 = (float)hist[lane] * dinv, d1 = (float)hist[lane + 64] * dinv;
     float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
     d0 = fminf(d0 / nrm, 0.2f);
     d1 = fminf(d1 / nrm, 0.2f);
     nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
-    float* out = I.desc + slot * 128;
-    out[lane] = d0 / nrm;
-    out[lane + 64] = d1 / nrm;
+    if (live) {
+        float* out = I.desc + slot * 128;
+        out[lane] = d0 / nrm;
+        out[lane + 64] = d1 / nrm;
+    }
 }
 
 size_t field_offset(const Geometry& g)
@@ -296,7 +370,8 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
         ta.r2[2 * s + 1] = g.s[s].r2_desc;
         ta.off[2 * s + 1] = g.s[s].off_desc;
     }
-    hipLaunchKernelGGL(disc_tables_kernel, dim3(ta.n_tables), dim3(256), 0, stream, ta, tables);
+    hipLaunchKernelGGL(disc_tables_kernel, dim3(ta.n_tables), dim3(kTabThreads), 0, stream, ta,
+                       tables);
     if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
     size_t foff = field_offset(g);
@@ -318,7 +393,7 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
             const lpsift_keypoints& kp = kps[b0 + i];
             da.img[i] = DescImg{field, im.height, im.width, kp.x, kp.y, theta[b0 + i], desc[b0 + i]};
         }
-        hipLaunchKernelGGL(polar_field_kernel, dim3((maxw + 63) / 64, maxh, nb), dim3(64), 0,
+        hipLaunchKernelGGL(polar_field_kernel, dim3((maxw + 255) / 256, maxh, nb), dim3(256), 0,
                            stream, fa);
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
@@ -342,8 +417,10 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
             da.img_begin[so][nb] = item;
         }
         da.scale_begin[g.n_scales] = item;
+        da.n_items = item;
         if (item > 0) {
-            hipLaunchKernelGGL(orient_describe_kernel, dim3((unsigned)item), dim3(64), 0, stream,
+            const unsigned blocks = (unsigned)((item + kWaves - 1) / kWaves);
+            hipLaunchKernelGGL(orient_describe_kernel, dim3(blocks), dim3(64 * kWaves), 0, stream,
                                da, tables);
             if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
         }
