@@ -35,7 +35,34 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=12288,
                     help="reference descriptors in the oracle's timed match sample")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before warm-up, copy a buffer of this size once (untimed): a plain "
+                         "copy kernel of known traffic for calibrating HBM counters")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_topk_f32_2600x1600_pair_traffic.md")
+MATCH_SRC = os.path.join(ROOT, "paper_2405_08578_amd", "csrc", "match.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the contraction kernel from the committed PMC
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = hashlib.sha256(open(MATCH_SRC, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("match.hip sha256") != sha:
+        return None
+    try:
+        return float(vals["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(pair, Ls, nq_sample):
@@ -106,6 +133,14 @@ def main():
         if ev is not None:
             ev[2].record(stream)
 
+    if args.copy_probe_mb > 0:
+        nb = args.copy_probe_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -152,7 +187,7 @@ def main():
         "matches": n_match,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(),
                      "kernel": "matcher call (norms + FP32 MFMA contraction/top-k + rescore), "
                                f"{flops / 1e9:.1f} GFLOP per call"},
     }
