@@ -45,7 +45,7 @@ enum {
 /* Method parameters (Sec. 2.2-2.3).
  *  n_scales  number of window sizes, 1..LPSIFT_MAX_SCALES
  *  L         window sides, strictly ascending, L[0] >= 4. On the GPU each L must
- *            divide the next and the largest must be <= 256 (nested windows).
+ *            divide the next and the largest must be <= 128 (nested windows).
  *  d         subregions per side of the descriptor square; only 4 is built.
  *  beta0     Eq. 3-4 size factor; <= 0 selects the largest admissible value
  *            (1/d) sqrt(Lmin/Lmax), for which w = d w_s <= L at every scale. */
@@ -118,7 +118,7 @@ int64_t lpsift_num_keypoints(int32_t height, int32_t width, const lpsift_params*
  *          lpsift_num_keypoints(image); every slot is written.
  * Errors: EINVAL (null pointer, n_images < 1, empty image, pitch < width, bad
  * params), ECAPACITY (capacity too small), EUNSUPPORTED (L set not nested or
- * Lmax > 256), EHIP. */
+ * Lmax > 128), EHIP. */
 int lpsift_detect(const lpsift_image* imgs, int32_t n_images, const lpsift_params* params,
                   const lpsift_keypoints* out, void* stream);
 
@@ -171,6 +171,25 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
                  const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
                  void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                  float* const* d2, void* stream);
+
+/* Homography between matched pairs by RANSAC (Sec. 2.5, Eq. 7), on the host in
+ * FP64; no GPU involvement and no stream. Eq. 8's rigid transform is the special
+ * case of a full homography (h33 = 1) fitted here.
+ *  xyA, xyB   host arrays of n (x, y) pairs: pair i maps A point i to B point i
+ *  samples    host [n_iter][4] indices into the pairs, the random draws of the
+ *             sampling loop (given by the caller, so runs are reproducible)
+ *  thresh     inlier iff the one-way reprojection error |H a - b| < thresh (px)
+ * Each non-degenerate sample (no 3 of its points nearly collinear in A or B)
+ * gives the exact homography through its 4 pairs (Hartley-normalised 8x8
+ * solve); the one with the most inliers (earliest on ties) is refined by least
+ * squares over its inliers. Outputs: H (host double[9], row-major, H[8] = 1;
+ * all zeros when no hypothesis was valid or n < 4), mask (host uint8[n], the
+ * inliers of the refined H), *n_inliers, *best_iter (-1 when none).
+ * Errors: EINVAL (null pointer, negative size, thresh not positive, sample
+ * index out of range when n >= 4). */
+int lpsift_ransac_host(const double* xyA, const double* xyB, int64_t n, const int32_t* samples,
+                       int32_t n_iter, double thresh, double* H, uint8_t* mask,
+                       int64_t* n_inliers, int32_t* best_iter);
 
 #ifdef __cplusplus
 }

@@ -53,7 +53,7 @@ class lpsift_match_params(ctypes.Structure):
 
 EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
            "lpsift_describe_workspace_size", "lpsift_describe", "lpsift_match_workspace_size",
-           "lpsift_match")
+           "lpsift_match", "lpsift_ransac_host")
 
 _lib = None
 
@@ -93,6 +93,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_match.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
                                  P(lpsift_match_params), c_vp, ctypes.c_size_t, P(c_vp), P(c_vp),
                                  P(c_vp), c_vp]
+    lib.lpsift_ransac_host.restype = ctypes.c_int
+    lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
+                                       P(c_i64), P(c_i32)]
     _lib = lib
     return lib
 
@@ -280,3 +283,23 @@ def features(images, params: Params, stream=None):
     kps = detect(images, params, stream=stream)
     theta, desc = describe(images, kps, params, stream=stream)
     return kps, theta, desc
+
+
+def ransac(xyA, xyB, samples, thresh: float = 3.0):
+    """Homography A -> B from matched pairs by RANSAC on the host (FP64).
+    xyA, xyB: [n, 2] arrays; samples: [n_iter, 4] int indices (the random
+    draws). Returns (H [3, 3] or None, inlier mask [n] bool, best iteration)."""
+    import numpy as np
+    lib = load()
+    a = np.ascontiguousarray(xyA, dtype=np.float64).reshape(-1, 2)
+    b = np.ascontiguousarray(xyB, dtype=np.float64).reshape(-1, 2)
+    if a.shape != b.shape:
+        raise ValueError("xyA and xyB must have the same shape")
+    smp = np.ascontiguousarray(samples, dtype=np.int32).reshape(-1, 4)
+    H = np.zeros(9, np.float64)
+    mask = np.zeros(len(a), np.uint8)
+    n_in, best = c_i64(), c_i32()
+    _check("lpsift_ransac_host", lib.lpsift_ransac_host(
+        a.ctypes.data, b.ctypes.data, len(a), smp.ctypes.data, len(smp), float(thresh),
+        H.ctypes.data, mask.ctypes.data, ctypes.byref(n_in), ctypes.byref(best)))
+    return (H.reshape(3, 3) if best.value >= 0 else None), mask.astype(bool), best.value

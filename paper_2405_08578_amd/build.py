@@ -34,6 +34,10 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def host_sources():
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".cpp"))
+
+
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in device code
@@ -45,11 +49,14 @@ FLAGS = [
 
 def _compile(src: str, asm: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):      # host-only C++
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", "-c", src, "-o", obj]
+    else:
+        cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
-    if asm:
+    if asm and src.endswith(".hip"):
         s = os.path.join(BUILD, os.path.basename(src) + ".s")
         subprocess.run([hipcc(), *FLAGS, "--cuda-device-only", "-S", src, "-o", s],
                        check=True, capture_output=True)
@@ -58,7 +65,7 @@ def _compile(src: str, asm: bool) -> str:
 
 def build(asm: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
+    srcs = sources() + host_sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, asm), srcs))
     tmp = LIB + ".tmp"

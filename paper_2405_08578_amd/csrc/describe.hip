@@ -132,18 +132,24 @@ struct DescImg {
 struct DescArgs {   // passed by value: keep well under 4 KB
     int32_t n_images;
     int32_t n_scales;
-    int64_t n_items;
     ScaleGeom geom[LPSIFT_MAX_SCALES];
-    // Work is ordered by scale, largest first, so the longest waves start first.
-    // Scale s (in that order) covers work items [scale_begin[s], scale_begin[s+1]).
-    int64_t scale_begin[LPSIFT_MAX_SCALES + 1];
-    int32_t scale_of[LPSIFT_MAX_SCALES];
-    // Within a scale, image i covers [img_begin[s][i], img_begin[s][i+1]) and its
-    // slots of that scale start at slot_base[s][i].
-    int64_t img_begin[LPSIFT_MAX_SCALES][kDescBatch + 1];
+    int32_t L[LPSIFT_MAX_SCALES];
+    // first slot of scale s in image i
     int64_t slot_base[LPSIFT_MAX_SCALES][kDescBatch];
     DescImg img[kDescBatch];
 };
+
+// Workgroup i runs on XCD i % 8 (round-robin dispatch). XCD x takes band x of
+// eight horizontal bands of window rows of every scale and image, largest
+// scale first: its L2 then holds one band of the gradient field, and every
+// XCD gets the same mix of scales.
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int64_t band_items(int x, int64_t nby, int64_t nbx)
+{
+    const int64_t r0 = (x * nby) / kXcds, r1 = ((x + 1) * nby) / kXcds;
+    return 2 * (r1 - r0) * nbx;
+}
 
 constexpr int kWaves = 4;          // keypoints per workgroup
 constexpr int kUnroll = 4;         // visits per lane per step
@@ -173,19 +179,31 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
 {
     __shared__ unsigned long long hist_all[kWaves][kBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t item_raw = (int64_t)blockIdx.x * kWaves + wave;
-    const bool live = item_raw < a.n_items;
-    const int64_t item = live ? item_raw : 0;
     unsigned long long* hist = hist_all[wave];
 
-    // locate (scale, image, slot) of this work item
-    int so = 0;
-    while (so + 1 < a.n_scales && item >= a.scale_begin[so + 1]) ++so;
-    int im = 0;
-    while (im + 1 < a.n_images && item >= a.img_begin[so][im + 1]) ++im;
-    const int64_t slot = a.slot_base[so][im] + (item - a.img_begin[so][im]);
+    // locate (scale, image, slot) of this wave's keypoint in its XCD's band list
+    const int xcd = blockIdx.x % kXcds;
+    int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + wave;
+    bool live = false;
+    int sc = 0, im = 0;
+    int64_t slot = 0;
+    for (int so = 0; so < a.n_scales && !live; ++so) {
+        const int s = a.n_scales - 1 - so;
+        for (int i = 0; i < a.n_images; ++i) {
+            const int64_t nby = n_windows(a.img[i].h, a.L[s]), nbx = n_windows(a.img[i].w, a.L[s]);
+            const int64_t cnt = band_items(xcd, nby, nbx);
+            if (j < cnt) {
+                live = true;
+                sc = s;
+                im = i;
+                slot = a.slot_base[s][i] + 2 * ((xcd * nby) / kXcds) * nbx + j;
+                break;
+            }
+            j -= cnt;
+        }
+    }
     const DescImg& I = a.img[im];
-    const ScaleGeom& G = a.geom[a.scale_of[so]];
+    const ScaleGeom& G = a.geom[sc];
     const int kx = I.x[slot], ky = I.y[slot];
     const float2* field = I.field;
     const int W = I.w, H = I.h;
@@ -397,31 +415,32 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
                            stream, fa);
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
-        // work items: scales from the largest, images in order within a scale
-        int64_t item = 0;
-        for (int so = 0; so < g.n_scales; ++so) {
-            const int s = g.n_scales - 1 - so;
+        // per-XCD band lists; the grid covers the longest one
+        int64_t longest = 0;
+        for (int s = 0; s < g.n_scales; ++s) {
             da.geom[s] = g.s[s];
-            da.scale_of[so] = s;
-            da.scale_begin[so] = item;
-            for (int i = 0; i < nb; ++i) {
-                const lpsift_image& im = imgs[b0 + i];
-                int64_t slot = 0;
-                for (int t = 0; t < s; ++t)
-                    slot += 2 * n_windows(im.height, g.L[t]) * n_windows(im.width, g.L[t]);
-                const int64_t cnt = 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
-                da.img_begin[so][i] = item;
-                da.slot_base[so][i] = slot;
-                item += cnt;
-            }
-            da.img_begin[so][nb] = item;
+            da.L[s] = g.L[s];
         }
-        da.scale_begin[g.n_scales] = item;
-        da.n_items = item;
-        if (item > 0) {
-            const unsigned blocks = (unsigned)((item + kWaves - 1) / kWaves);
-            hipLaunchKernelGGL(orient_describe_kernel, dim3(blocks), dim3(64 * kWaves), 0, stream,
-                               da, tables);
+        for (int i = 0; i < nb; ++i) {
+            const lpsift_image& im = imgs[b0 + i];
+            int64_t slot = 0;
+            for (int s = 0; s < g.n_scales; ++s) {
+                da.slot_base[s][i] = slot;
+                slot += 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
+            }
+        }
+        for (int x = 0; x < kXcds; ++x) {
+            int64_t items = 0;
+            for (int s = 0; s < g.n_scales; ++s)
+                for (int i = 0; i < nb; ++i)
+                    items += band_items(x, n_windows(imgs[b0 + i].height, g.L[s]),
+                                        n_windows(imgs[b0 + i].width, g.L[s]));
+            longest = items > longest ? items : longest;
+        }
+        if (longest > 0) {
+            const int64_t per_xcd = (longest + kWaves - 1) / kWaves;
+            hipLaunchKernelGGL(orient_describe_kernel, dim3((unsigned)(per_xcd * kXcds)),
+                               dim3(64 * kWaves), 0, stream, da, tables);
             if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
         }
     }

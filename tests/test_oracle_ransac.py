@@ -1,0 +1,75 @@
+"""Pins of the oracle's RANSAC homography (Sec. 2.5, Eq. 7-8)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ransac as R
+
+
+def rand_h(rng):
+    H = synth.similarity_h(rng.uniform(-20, 20), rng.uniform(0.8, 1.2), rng.uniform(-200, 200),
+                           rng.uniform(-100, 100))
+    H[2, :2] = rng.uniform(-2e-5, 2e-5, 2)     # mild projective part
+    return H
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_dlt_recovers_exact_homography(seed):
+    rng = np.random.default_rng(seed)
+    H = rand_h(rng)
+    pa = rng.uniform(0, 2000, (4, 2))
+    pb = synth.apply_h(H, pa)
+    G = R.dlt(pa, pb)
+    assert np.allclose(G, H / H[2, 2], rtol=1e-9, atol=1e-9)
+    pa = rng.uniform(0, 2000, (50, 2))
+    G = R.dlt(pa, synth.apply_h(H, pa))
+    assert np.allclose(G, H / H[2, 2], rtol=1e-9, atol=1e-9)
+
+
+def test_rigid_transform_of_eq8_is_recovered():
+    # Eq. 8: rotation and translation only
+    H = synth.similarity_h(12.0, 1.0, 35.0, -7.0)
+    pa = np.random.default_rng(1).uniform(0, 500, (30, 2))
+    G = R.dlt(pa, synth.apply_h(H, pa))
+    th = np.degrees(np.arctan2(G[1, 0], G[0, 0]))
+    assert th == pytest.approx(12.0, abs=1e-9)
+    assert G[0, 2] == pytest.approx(35.0, abs=1e-7) and G[1, 2] == pytest.approx(-7.0, abs=1e-7)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_planted_inliers_among_outliers(seed):
+    rng = np.random.default_rng(10 + seed)
+    H = rand_h(rng)
+    n_in, n_out = 60, 140
+    pa = rng.uniform(0, 2000, (n_in + n_out, 2))
+    pb = synth.apply_h(H, pa)
+    pb[:n_in] += rng.normal(0, 0.3, (n_in, 2))
+    pb[n_in:] = rng.uniform(-500, 2500, (n_out, 2))
+    perm = rng.permutation(n_in + n_out)
+    pa, pb = pa[perm], pb[perm]
+    truth = perm < n_in
+    samples = synth.ransac_samples(len(pa), 2000, np.random.default_rng(seed))
+    G, mask, best = R.ransac(pa, pb, samples, 3.0)
+    assert best >= 0
+    assert np.array_equal(mask, truth)
+    corners = np.array([[0, 0], [2000, 0], [2000, 2000], [0, 2000.0]])
+    assert np.abs(synth.apply_h(G, corners) - synth.apply_h(H, corners)).max() < 1.0
+
+
+def test_degenerate_samples_are_skipped():
+    pa = np.array([[0, 0], [1, 1], [2, 2], [3, 3], [0, 5.0]])
+    pb = pa + 1.0
+    G, mask, best = R.ransac(pa, pb, np.array([[0, 1, 2, 3]]), 3.0)
+    assert G is None and best == -1 and not mask.any()
+    G, mask, best = R.ransac(pa, pb, np.array([[0, 1, 2, 3], [0, 1, 4, 3]]), 3.0)
+    # the second sample has 0, 1, 3 collinear too
+    assert G is None
+    pa = np.array([[0, 0], [10, 0], [0, 10], [10, 10], [5, 3.0]])
+    G, mask, best = R.ransac(pa, pa + [2.0, -1.0], np.array([[0, 1, 2, 3]]), 3.0)
+    assert best == 0 and mask.all()
+    assert np.allclose(G, [[1, 0, 2], [0, 1, -1], [0, 0, 1]], atol=1e-12)
+
+
+def test_too_few_points():
+    G, mask, best = R.ransac(np.zeros((3, 2)), np.zeros((3, 2)), np.zeros((5, 4), np.int32), 3.0)
+    assert G is None and len(mask) == 3
