@@ -191,6 +191,38 @@ def main():
                      "kernel": "matcher call (norms + FP32 MFMA contraction/top-k + rescore), "
                                f"{flops / 1e9:.1f} GFLOP per call"},
     }
+    # reduced-precision contractions on the same descriptors (side fields): the
+    # split BF16x3 path is certified against the FP32 path, BF16 and FP8 are
+    # approximate
+    ref = mout[0]["match"].clone()
+    lowp = {}
+    for prec, name in ((3, "split_bf16x3_certified"), (1, "bf16"), (2, "fp8")):
+        mpl = lp.match_params(precision=prec)
+        wsl = torch.empty(lp.match_workspace_size([n_kp], [n_kp], mpl), dtype=torch.uint8, device=dev)
+        outl = [{k: torch.empty_like(v) for k, v in mout[0].items()}]
+        stats = torch.zeros(1, dtype=torch.int32, device=dev)
+        call = lambda: lp.match([desc[0]], [desc[1]], precision=prec, workspace=wsl, out=outl,
+                                stream=stream, stats=stats)
+        for _ in range(max(1, args.warmup)):
+            call()
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        for _ in range(args.steps):
+            call()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1]) / args.steps
+        same = (outl[0]["match"] == ref).float().mean().item()
+        lowp[name] = {"match_ms": round(ms, 4),
+                      "pairs_per_s": round(1000.0 / (dd_avg + ms), 2),
+                      "contraction_tflops_equiv": round(flops / (ms * 1e-3) / 1e12, 1),
+                      "list_agreement_with_fp32": round(same, 6)}
+        if prec == 3:
+            lowp[name]["queries_rematched_fp32"] = int(stats.item())
+        del wsl, outl
+    out["low_precision_match"] = lowp
+
     if not args.no_cpu_baseline:
         cb = cpu_baseline(pair, Ls, args.cpu_queries)
         out["cpu_baseline"] = {k: (round(v, 6) if isinstance(v, float) else v)

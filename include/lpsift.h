@@ -88,13 +88,28 @@ typedef struct lpsift_keypoints {
 /* Matching parameters (Sec. 2.4, Eq. 6).
  *  ratio       a query is kept when d1 < ratio * d2 (compared in double)
  *  abs_thresh  ... and d1 < abs_thresh (the Delta_s of Eq. 6; +inf disables it)
- *  precision   0 = FP32 distance contraction (the only one built so far)
- *  b_chunks    candidate-range split of the contraction; 0 = automatic */
+ *  precision   contraction used to select candidates (d1 and d2 are always
+ *              direct FP32 distances of the selected candidates):
+ *              0 = FP32 matrix cores; exact up to FP32 rounding.
+ *              1 = BF16 inputs, FP32 accumulation; the 8 best kept candidates
+ *                  per query are rescored: approximate (a true nearest
+ *                  neighbour can be missed).
+ *              2 = FP8 E4M3 inputs with one scale per descriptor, FP32
+ *                  accumulation, 8 candidates rescored: approximate.
+ *              3 = FP32 split into two BF16 parts (three BF16 products per
+ *                  term, FP32 accumulation), certified per query by an error
+ *                  bound; queries it cannot certify are re-matched with
+ *                  precision 0, so the lists equal precision 0's.
+ *  b_chunks    candidate-range split of the contraction (0 = automatic, <= 16)
+ *  stats       optional device pointer to one uint32: after the call (stream
+ *              order) it holds the number of queries of the last pair that
+ *              precision 3 re-matched with precision 0 (0 otherwise) */
 typedef struct lpsift_match_params {
     double ratio;
     float abs_thresh;
     int32_t precision;
     int32_t b_chunks;
+    void* stats;
 } lpsift_match_params;
 
 /* Library version as 10000*major + 100*minor + patch. Host only. */
@@ -162,11 +177,13 @@ size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t
  * smallest distance over the other registered descriptors (+inf if there is
  * none). match[i] = j1 when d1 < ratio * d2 and d1 < abs_thresh, else -1.
  * d1 and d2 are FP32 distances sqrt(sum (a-b)^2) recomputed directly for the
- * best candidates of an FP32 matrix-core contraction.
+ * best candidates of a matrix-core contraction (see precision).
  *  descA, descB  host arrays of n_pairs device pointers to float[n][128]
  *  nA, nB        host arrays of n_pairs counts (nA >= 0, nB >= 0)
  *  match, d1, d2 host arrays of n_pairs device pointers to int32/float[nA]
- * Errors: EINVAL, ECAPACITY (workspace), EUNSUPPORTED (precision != 0), EHIP. */
+ * Errors: EINVAL (null pointer, negative count, descriptor pointer not 16-byte
+ * aligned, workspace not 256-byte aligned, bad ratio/abs_thresh/precision),
+ * ECAPACITY (workspace), EHIP. */
 int lpsift_match(const float* const* descA, const int64_t* nA, const float* const* descB,
                  const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
                  void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,

@@ -48,7 +48,7 @@ class lpsift_keypoints(ctypes.Structure):
 
 class lpsift_match_params(ctypes.Structure):
     _fields_ = [("ratio", c_f64), ("abs_thresh", c_f32), ("precision", c_i32),
-                ("b_chunks", c_i32)]
+                ("b_chunks", c_i32), ("stats", c_vp)]
 
 
 EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
@@ -231,12 +231,13 @@ def describe(images, kps, params: Params, workspace=None, theta=None, desc=None,
 
 
 def match_params(ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
-                 b_chunks: int = 0) -> lpsift_match_params:
+                 b_chunks: int = 0, stats=None) -> lpsift_match_params:
     mp = lpsift_match_params()
     mp.ratio = ratio
     mp.abs_thresh = abs_thresh
     mp.precision = precision
     mp.b_chunks = b_chunks
+    mp.stats = None if stats is None else stats.data_ptr()
     return mp
 
 
@@ -247,9 +248,11 @@ def match_workspace_size(nA: Sequence[int], nB: Sequence[int], mp: lpsift_match_
 
 
 def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
-          b_chunks: int = 0, workspace=None, out=None, stream=None) -> List[Dict[str, "object"]]:
+          b_chunks: int = 0, workspace=None, out=None, stream=None,
+          stats=None) -> List[Dict[str, "object"]]:
     """Nearest neighbour of every row of descA[p] among descB[p] with the ratio
-    test, for every pair p."""
+    test, for every pair p. stats: optional int32 CUDA tensor [1] that receives
+    the number of queries the BF16 path re-matched in FP32."""
     import torch
     lib = load()
     n = len(descA)
@@ -260,7 +263,7 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
                 or not t.is_contiguous():
             raise ValueError("descriptors must be contiguous float32 CUDA tensors [n, 128]")
     dev = descA[0].device
-    mp = match_params(ratio, abs_thresh, precision, b_chunks)
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
     nA = [int(t.shape[0]) for t in descA]
     nB = [int(t.shape[0]) for t in descB]
     need = match_workspace_size(nA, nB, mp)

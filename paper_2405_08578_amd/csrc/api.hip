@@ -167,8 +167,7 @@ static int check_match_params(const lpsift_match_params* mp)
     if (!(mp->ratio > 0.0) || !std::isfinite(mp->ratio)) return LPSIFT_EINVAL;
     if (std::isnan(mp->abs_thresh) || !(mp->abs_thresh > 0.0f)) return LPSIFT_EINVAL;
     if (mp->b_chunks < 0 || mp->b_chunks > 16) return LPSIFT_EINVAL;
-    if (mp->precision < 0 || mp->precision > 2) return LPSIFT_EINVAL;
-    if (mp->precision != 0) return LPSIFT_EUNSUPPORTED;
+    if (mp->precision < 0 || mp->precision > 3) return LPSIFT_EINVAL;
     return LPSIFT_OK;
 }
 

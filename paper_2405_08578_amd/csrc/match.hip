@@ -3,52 +3,106 @@
 // |a - b|^2 = |a|^2 + |b|^2 - 2 a.b, and |a|^2 is constant per query, so the
 // nearest candidates of a query are those with the smallest |b|^2 - 2 a.b.
 // The a.b contraction is a GEMM of the two descriptor sets and runs on the
-// matrix cores (v_mfma_f32_32x32x2_f32, FP32 in and out):
+// matrix cores; the N_A x N_B score matrix is never stored.
 //
+// FP32 path (precision 0), v_mfma_f32_32x32x2_f32:
 //  * the MFMA's A operand is a 32-candidate tile (rows) and its B operand 32
 //    queries (columns), so lane l of the 32x32 result holds 16 candidates of
-//    one query (l % 32): the top-2 bookkeeping is private to each lane and the
-//    N_A x N_B score matrix is never stored;
+//    one query (l % 32): the top-2 bookkeeping is private to each lane;
 //  * a wavefront keeps 2 x 32 queries in registers for the whole sweep (the K
 //    dimension split in halves: lanes 0-31 carry k = 0..63, lanes 32-63 carry
 //    k = 64..127 -- any permutation of K shared by both operands leaves the
 //    dot products unchanged);
 //  * a 256-thread workgroup (4 wavefronts, 256 queries) streams the candidates
-//    of its chunk through LDS, 32 at a time, with the next tile prefetched into
-//    registers while the current one is contracted;
-//  * the candidate range is split into chunks so that the grid fills the chip.
+//    of its chunk through LDS, 32 at a time, the next tile prefetched into
+//    registers while the current one is contracted; the candidate range is
+//    split into chunks so that the grid fills the chip.
+//  Each lane's top-2 of each chunk survives (4 candidates per query and
+//  chunk). The rescore kernel keeps the 4 best by contraction score,
+//  recomputes their squared distances directly in FP32, takes the two
+//  smallest (lowest index on ties) and applies d1 < ratio * d2 in double.
 //
-// Each lane's top-2 of each chunk survives (4 candidates per query and chunk).
-// The rescore kernel keeps the 4 best by contraction score, recomputes their
-// squared distances directly in FP32, takes the two smallest (lowest index on
-// ties) and applies d1 < ratio * d2 in double precision.
+// Quantised paths (approximate): BF16 (precision 1, v_mfma_f32_32x32x16_bf16)
+// and FP8 E4M3 with one scale per descriptor (precision 2,
+// v_mfma_f32_32x32x64_f8f6f4), FP32 accumulation, 4 x 32 queries per wavefront.
+// At these rates the VALU can afford ~4 instructions per contraction output, so
+// each output becomes one 32-bit key -- the score's float bits with the low
+// bits replaced by the candidate's index in its chunk -- and a lane's top-2 is
+// kept with an unsigned min and med3 (the score carries an offset C that makes
+// it positive, so float bits order like values). The 8 best kept candidates of
+// a query are rescored in FP32; a true nearest neighbour can be missed.
+//
+// Split path (precision 3, exact): each FP32 value is split into two BF16
+// parts, a.b ~ hi.hi + hi.lo + lo.hi (three BF16 MFMAs, FP32 accumulation),
+// which is ~5x cheaper than the FP32 contraction and accurate to ~1e-4. Each
+// lane keeps exact float scores (top-2 with indices plus its third-best score).
+// From the split errors a per-query bound E on every score error follows; if
+// everything a lane did not keep scores above the kept second best by more
+// than 2E, the true two nearest are among the kept ones and FP32 rescoring of
+// those is exact. Other queries go to a device-side list matched by the FP32
+// path. The lists equal the FP32 path's.
 #include "internal.h"
 
 namespace lpsift {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
 
-constexpr int kQB = 256;        // queries per workgroup
-constexpr int kCT = 32;         // candidates per LDS tile
-constexpr int kRow = 128 + 4;   // padded LDS row (floats)
-constexpr int kKeep = 4;        // candidates kept per (query, chunk)
+constexpr int kQB = 256;        // FP32: queries per workgroup
+constexpr int kCT = 32;         // FP32: candidates per LDS tile
+constexpr int kRow = 128 + 4;   // FP32: padded LDS row (floats)
+constexpr int kKeep = 4;        // FP32: candidates kept per (query, chunk)
 
-__global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ B, int64_t n,
-                                                     float* __restrict__ out)
+// Relative bound on the BF16 contraction error per unit |a||b|: 2u + u^2 +
+// 128 x 2^-24 with u = 2^-8 (used to keep the quantised paths' scores positive).
+constexpr float kBf16DotErr = 0.00785f;
+
+// ------------------------------------------------------------------ common --
+
+// Zeroes the per-call counters (used instead of a memset so the whole call
+// can be captured in a graph).
+__global__ void init_counters_kernel(uint32_t* c, int n)
 {
-    // 16 lanes per row, 8 floats each
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+
+__global__ void copy_u32_kernel(uint32_t* dst, const uint32_t* src) { *dst = *src; }
+
+// Maximum of v over the 256-thread workgroup, merged into *dst with one
+// atomic per workgroup (v: bits of non-negative floats, which order like
+// unsigned integers).
+__device__ inline void block_max_atomic(uint32_t* dst, uint32_t v)
+{
+    __shared__ uint32_t red[4];
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(dst, max(max(red[0], red[1]), max(red[2], red[3])));
+    __syncthreads();
+}
+
+// |x|^2 of every row (optional output) and the maximum over rows, as the bit
+// pattern of a non-negative float (bits order like values), 16 lanes per row.
+__global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X, int64_t n,
+                                                     float* __restrict__ out,
+                                                     uint32_t* __restrict__ maxbits)
+{
     const int64_t row = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
     const int part = threadIdx.x % 16;
     float s = 0.0f;
     if (row < n) {
-        const float4* p = reinterpret_cast<const float4*>(B + row * 128 + part * 8);
+        const float4* p = reinterpret_cast<const float4*>(X + row * 128 + part * 8);
         const float4 a = p[0], b = p[1];
         s = a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w + b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w;
     }
     for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-    if (row < n && part == 0) out[row] = s;
+    if (row < n && part == 0 && out) out[row] = s;
+    if (maxbits) block_max_atomic(maxbits, __float_as_uint(s));   // rows beyond n have s = 0
 }
+
+// ---------------------------------------------------------------- FP32 path --
 
 // Branch-free insertion into a (score, index) top-2; on equal scores the
 // earlier (lower) index stays first because candidates arrive in index order.
@@ -62,18 +116,25 @@ __device__ inline void top2_push(float s, int j, float& s1, int& j1, float& s2, 
     j1 = lt1 ? j : j1;
 }
 
+// qlist/qcount (optional): match only the queries qlist[0 .. *qcount); results
+// for list entry i are stored at position i.
 __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(
     const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int64_t nB,
     const float* __restrict__ nrmB, int64_t chunk_len, int chunks,
+    const int32_t* __restrict__ qlist, const uint32_t* __restrict__ qcount,
     int32_t* __restrict__ cidx, float* __restrict__ cscore)
 {
     __shared__ __attribute__((aligned(16))) float tile[kCT * kRow];
     __shared__ float tnrm[kCT];
+    const int64_t nq = qlist ? (int64_t)*qcount : nA;
+    if ((int64_t)blockIdx.x * kQB >= nq) return;   // whole workgroup
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t q0 = (int64_t)blockIdx.x * kQB + wave * 64 + col;
-    const int64_t q1 = q0 + 32;
+    const int64_t i0 = (int64_t)blockIdx.x * kQB + wave * 64 + col;
+    const int64_t i1 = i0 + 32;
+    const int64_t q0 = (i0 < nq) ? (qlist ? qlist[i0] : i0) : -1;
+    const int64_t q1 = (i1 < nq) ? (qlist ? qlist[i1] : i1) : -1;
     const int chunk = blockIdx.y;
     const int64_t cb = (int64_t)chunk * chunk_len;
     const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
@@ -85,8 +146,8 @@ __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(
         const float4* pb = reinterpret_cast<const float4*>(A + q1 * 128 + h * 64);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const float4 va = (q0 < nA) ? pa[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            const float4 vb = (q1 < nA) ? pb[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 va = (q0 >= 0) ? pa[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 vb = (q1 >= 0) ? pb[i] : make_float4(0.f, 0.f, 0.f, 0.f);
             qa[4 * i + 0] = va.x; qa[4 * i + 1] = va.y; qa[4 * i + 2] = va.z; qa[4 * i + 3] = va.w;
             qb[4 * i + 0] = vb.x; qb[4 * i + 1] = vb.y; qb[4 * i + 2] = vb.z; qb[4 * i + 3] = vb.w;
         }
@@ -152,45 +213,98 @@ __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(
     }
 
     // candidates of padded rows carry score +inf and are never pushed
-    if (q0 < nA) {
-        const int64_t o = (q0 * chunks + chunk) * kKeep + 2 * h;
+    if (q0 >= 0) {
+        const int64_t o = (i0 * chunks + chunk) * kKeep + 2 * h;
         cidx[o] = ja1; cidx[o + 1] = ja2;
         cscore[o] = sa1; cscore[o + 1] = sa2;
     }
-    if (q1 < nA) {
-        const int64_t o = (q1 * chunks + chunk) * kKeep + 2 * h;
+    if (q1 >= 0) {
+        const int64_t o = (i1 * chunks + chunk) * kKeep + 2 * h;
         cidx[o] = jb1; cidx[o + 1] = jb2;
         cscore[o] = sb1; cscore[o + 1] = sb2;
     }
 }
 
-// One wavefront per query: keep the 4 best candidates by contraction score,
-// recompute their distances directly, then the ratio test.
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Direct FP32 squared distance of query row a (lanes hold a0 = a[lane],
+// a1 = a[64 + lane]) to candidate j, summed across the wavefront.
+__device__ inline float sqdist(float a0, float a1, const float* __restrict__ B, int64_t j, int lane)
+{
+    const float x0 = a0 - B[j * 128 + lane], x1 = a1 - B[j * 128 + 64 + lane];
+    return wave_sum(x0 * x0 + x1 * x1);
+}
+
+// ordered insert by (squared distance, index)
+__device__ inline void best2_insert(float s, int j, float& e1, int& j1, float& e2, int& j2)
+{
+    if (s < e1 || (s == e1 && j < j1)) {
+        e2 = e1; j2 = j1;
+        e1 = s; j1 = j;
+    } else if (s < e2 || (s == e2 && j < j2)) {
+        e2 = s; j2 = j;
+    }
+}
+
+__device__ inline void write_result(int64_t q, float e1, int j1, float e2, double ratio,
+                                    float abs_thresh, int32_t* match, float* d1out, float* d2out)
+{
+    const float dd1 = sqrtf(e1), dd2 = sqrtf(e2);
+    const bool keep = j1 >= 0 && (double)dd1 < ratio * (double)dd2 && dd1 < abs_thresh;
+    match[q] = keep ? j1 : -1;
+    d1out[q] = dd1;
+    d2out[q] = dd2;
+}
+
+// One wavefront per query: keep the 4 best candidates by contraction score
+// (chunks x 4 entries, up to 256: 4 per lane), recompute their distances
+// directly, then the ratio test.
 __global__ __launch_bounds__(256) void rescore_kernel(
     const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int chunks,
+    const int32_t* __restrict__ qlist, const uint32_t* __restrict__ qcount,
     const int32_t* __restrict__ cidx, const float* __restrict__ cscore, double ratio,
     float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
     float* __restrict__ d2out)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nA) return;
-    const int nc = chunks * kKeep;   // <= 64
-    float sc = INFINITY;
-    int id = -1;
-    if (lane < nc) {
-        id = cidx[q * nc + lane];
-        sc = (id >= 0) ? cscore[q * nc + lane] : INFINITY;
-        if (id < 0) id = 0x7FFFFFFF;
-    } else {
-        id = 0x7FFFFFFF;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nq = qlist ? (int64_t)*qcount : nA;
+    if (i >= nq) return;
+    const int64_t q = qlist ? qlist[i] : i;
+    const int nc = chunks * kKeep;   // <= 256
+    float sc[4];
+    int id[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k;
+        sc[k] = INFINITY;
+        id[k] = 0x7FFFFFFF;
+        if (e < nc) {
+            const int c = cidx[i * nc + e];
+            if (c >= 0) {
+                id[k] = c;
+                sc[k] = cscore[i * nc + e];
+            }
+        }
     }
     const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
     float e1 = INFINITY, e2 = INFINITY;
     int j1 = -1, j2 = -1;
     for (int round = 0; round < 4; ++round) {
-        float bs = sc;
-        int bi = id;
+        // this lane's best entry, then the wavefront's
+        float bs = sc[0];
+        int bi = id[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (sc[k] < bs || (sc[k] == bs && id[k] < bi)) {
+                bs = sc[k];
+                bi = id[k];
+            }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const float os = __shfl_xor(bs, off);
@@ -201,36 +315,584 @@ __global__ __launch_bounds__(256) void rescore_kernel(
             }
         }
         if (bi == 0x7FFFFFFF || bs == INFINITY) break;
-        if (id == bi) sc = INFINITY, id = 0x7FFFFFFF;   // taken
-        const float b0 = B[(int64_t)bi * 128 + lane], b1 = B[(int64_t)bi * 128 + 64 + lane];
-        const float x0 = a0 - b0, x1 = a1 - b1;
-        float s = x0 * x0 + x1 * x1;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        // ordered insert by (squared distance, index)
-        if (s < e1 || (s == e1 && bi < j1)) {
-            e2 = e1; j2 = j1;
-            e1 = s; j1 = bi;
-        } else if (s < e2 || (s == e2 && bi < j2)) {
-            e2 = s; j2 = bi;
-        }
+        for (int k = 0; k < 4; ++k)
+            if (id[k] == bi) sc[k] = INFINITY, id[k] = 0x7FFFFFFF;   // taken (ids are unique)
+        best2_insert(sqdist(a0, a1, B, bi, lane), bi, e1, j1, e2, j2);
     }
-    if (lane == 0) {
-        const float dd1 = sqrtf(e1), dd2 = sqrtf(e2);
-        const bool keep = j1 >= 0 && (double)dd1 < ratio * (double)dd2 && dd1 < abs_thresh;
-        match[q] = keep ? j1 : -1;
-        d1out[q] = dd1;
-        d2out[q] = dd2;
+    if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
+}
+
+// ------------------------------------------------------ low-precision paths --
+
+template <int P> struct Lp;
+template <> struct Lp<1> {             // BF16
+    static constexpr int kRowBytes = 256;
+    static constexpr int kOpBytes = 16;  // operand bytes per lane per MFMA
+    static constexpr int kSteps = 8;     // MFMAs per 32 x 32 block over K = 128
+    static constexpr int kKStep = 16;    // K per MFMA
+    static constexpr int kEsize = 2;
+};
+template <> struct Lp<2> {             // FP8 E4M3
+    static constexpr int kRowBytes = 128;
+    static constexpr int kOpBytes = 32;
+    static constexpr int kSteps = 2;
+    static constexpr int kKStep = 64;
+    static constexpr int kEsize = 1;
+};
+
+// BF16 bits of x, rounded to nearest even (finite x).
+__device__ inline uint32_t bf16_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+constexpr int kLpSets = 4;                         // 32-query sets per wavefront
+constexpr int kLpKeepBf16 = 2;                     // keys kept per lane: BF16 ...
+constexpr int kLpKeepFp8 = 2;                      // ... and FP8
+constexpr int kLpRescore = 8;                      // kept candidates rescored in FP32
+constexpr int kLpQB = 4 * 32 * kLpSets;            // queries per workgroup (512)
+constexpr int kLpCT = 64;                          // candidates per LDS tile
+constexpr float kFp8Max = 448.0f;                  // largest finite E4M3 value
+
+// Quantise rows of 128 floats: BF16 (round to nearest even) or FP8 E4M3 with
+// the per-row scale max|x| / 448. 16 lanes per row, 8 values each.
+template <int P>
+__global__ __launch_bounds__(256) void quantize_kernel(const float* __restrict__ X, int64_t n,
+                                                       uint8_t* __restrict__ Y,
+                                                       float* __restrict__ scale,
+                                                       uint32_t* __restrict__ max_err2)
+{
+    const int64_t row = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+    const int part = threadIdx.x % 16;
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (row < n) {
+        const float4* p = reinterpret_cast<const float4*>(X + row * 128 + part * 8);
+        const float4 a = p[0], b = p[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+    if (P == 1) {
+        uint32_t w[4];
+        float e2 = 0.0f;   // |x - bf16(x)|^2 of this row part (each difference is exact)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t lo = bf16_bits(v[2 * k]), hi = bf16_bits(v[2 * k + 1]);
+            const float dl = v[2 * k] - __uint_as_float(lo << 16);
+            const float dh = v[2 * k + 1] - __uint_as_float(hi << 16);
+            e2 += dl * dl + dh * dh;
+            w[k] = lo | (hi << 16);
+        }
+        for (int off = 8; off > 0; off >>= 1) e2 += __shfl_xor(e2, off, 16);
+        if (row < n) {
+            *reinterpret_cast<uint4*>(Y + row * 256 + part * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+            if (part == 0 && max_err2) atomicMax(max_err2, __float_as_uint(e2 * 1.0001f));
+        }
+    } else {
+        float m = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m = fmaxf(m, fabsf(v[k]));
+        for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 16));
+        const float s = (m > 0.0f) ? m / kFp8Max : 1.0f;
+        const float inv = (m > 0.0f) ? kFp8Max / m : 1.0f;
+        float x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = fminf(fmaxf(v[k] * inv, -kFp8Max), kFp8Max);
+        int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+        w0 = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], w0, true);
+        int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(x[4], x[5], 0, false);
+        w1 = __builtin_amdgcn_cvt_pk_fp8_f32(x[6], x[7], w1, true);
+        const uint32_t w[2] = {(uint32_t)w0, (uint32_t)w1};
+        if (row < n) {
+            *reinterpret_cast<uint2*>(Y + row * 128 + part * 8) = make_uint2(w[0], w[1]);
+            if (part == 0) scale[row] = s;
+        }
     }
 }
 
-struct WsLayout {
+// Contraction + per-lane top-K of packed keys for one (query block, chunk).
+// keys[((i * chunks + chunk) * 2 + h) * K + {0 .. K-1}] = lane half h's best K
+// keys of query i, ascending (0xFFFFFFFF = none). key = (float bits of score & ~idx_mask) | index
+// in chunk, score = |b|^2 + C - 2 a.b > 0 (C from the per-call scalars).
+template <int P, int K>
+__global__ __launch_bounds__(256, 1) void match_topk_lp_kernel(
+    const uint8_t* __restrict__ Aq, const float* __restrict__ sA, int64_t nA,
+    const uint8_t* __restrict__ Bq, const float* __restrict__ sB, int64_t nB,
+    const float* __restrict__ nrmB, const float* __restrict__ scal, int64_t chunk_len,
+    int chunks, uint32_t idx_mask, uint32_t* __restrict__ keys)
+{
+    using T = Lp<P>;
+    constexpr int kLRow = T::kRowBytes + 16;   // padded LDS row
+    constexpr int kU4 = kLpCT * T::kRowBytes / 16 / 256;   // uint4 per thread per tile
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kLpCT * kLRow];
+    __shared__ float tnb[kLpCT];
+    __shared__ float tsb[kLpCT];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int chunk = blockIdx.y;
+    const int64_t cb = (int64_t)chunk * chunk_len;
+    const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
+    const float C = scal[0];
+
+    // queries: set t, operand step s -> bytes [(s*KStep + h*KStep/2)*esize, +OpBytes)
+    constexpr int kQRegs = T::kOpBytes / 16;   // uint4 per operand
+    uint4 qv[kLpSets][T::kSteps][kQRegs];
+    float qs2[kLpSets];                         // -2 x query scale (FP8)
+    int64_t qi[kLpSets];
+#pragma unroll
+    for (int t = 0; t < kLpSets; ++t) {
+        const int64_t q = (int64_t)blockIdx.x * kLpQB + wave * (32 * kLpSets) + t * 32 + col;
+        qi[t] = q;
+        const uint8_t* row = Aq + q * T::kRowBytes;
+#pragma unroll
+        for (int s = 0; s < T::kSteps; ++s)
+#pragma unroll
+            for (int u = 0; u < kQRegs; ++u)
+                qv[t][s][u] = (q < nA) ? *reinterpret_cast<const uint4*>(
+                                             row + (s * T::kKStep + h * T::kKStep / 2) * T::kEsize + 16 * u)
+                                       : make_uint4(0u, 0u, 0u, 0u);
+        qs2[t] = (P == 2) ? -2.0f * ((q < nA) ? sA[q] : 0.0f) : -2.0f;
+    }
+    uint32_t k1[kLpSets], k2[kLpSets], k3[kLpSets];
+#pragma unroll
+    for (int t = 0; t < kLpSets; ++t) {
+        k1[t] = 0xFFFFFFFFu;
+        k2[t] = 0xFFFFFFFFu;
+        k3[t] = 0xFFFFFFFFu;
+    }
+
+    uint4 pf[kU4];
+    auto fetch = [&](int64_t t0) {
+#pragma unroll
+        for (int k = 0; k < kU4; ++k) {
+            const int f = tid + 256 * k;
+            const int r = f / (T::kRowBytes / 16), c16 = f % (T::kRowBytes / 16);
+            const int64_t j = t0 + r;
+            pf[k] = (j < ce) ? reinterpret_cast<const uint4*>(Bq + j * T::kRowBytes)[c16]
+                             : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    if (cb < ce) fetch(cb);
+
+    for (int64_t t0 = cb; t0 < ce; t0 += kLpCT) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kU4; ++k) {
+            const int f = tid + 256 * k;
+            const int r = f / (T::kRowBytes / 16), c16 = f % (T::kRowBytes / 16);
+            *reinterpret_cast<uint4*>(&tile[r * kLRow + c16 * 16]) = pf[k];
+        }
+        if (tid < kLpCT) {
+            const int64_t j = t0 + tid;
+            tnb[tid] = (j < ce) ? nrmB[j] + C : INFINITY;
+            tsb[tid] = (P == 2 && j < ce) ? sB[j] : 1.0f;
+        }
+        __syncthreads();
+        if (t0 + kLpCT < ce) fetch(t0 + kLpCT);
+        const uint32_t local0 = (uint32_t)(t0 - cb);
+
+#pragma unroll
+        for (int sub = 0; sub < kLpCT / 32; ++sub) {
+            floatx16 acc[kLpSets];
+#pragma unroll
+            for (int t = 0; t < kLpSets; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+            const uint8_t* trow = &tile[(sub * 32 + col) * kLRow];
+#pragma unroll
+            for (int s = 0; s < T::kSteps; ++s) {
+                uint4 av[kQRegs];
+#pragma unroll
+                for (int u = 0; u < kQRegs; ++u)
+                    av[u] = *reinterpret_cast<const uint4*>(
+                        trow + (s * T::kKStep + h * T::kKStep / 2) * T::kEsize + 16 * u);
+#pragma unroll
+                for (int t = 0; t < kLpSets; ++t) {
+                    if constexpr (P == 1) {
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, av[0]), __builtin_bit_cast(bf16x8, qv[t][s][0]),
+                            acc[t], 0, 0, 0);
+                    } else {
+                        const intx8 a8 = {(int)av[0].x, (int)av[0].y, (int)av[0].z, (int)av[0].w,
+                                          (int)av[1].x, (int)av[1].y, (int)av[1].z, (int)av[1].w};
+                        const intx8 b8 = {(int)qv[t][s][0].x, (int)qv[t][s][0].y, (int)qv[t][s][0].z,
+                                          (int)qv[t][s][0].w, (int)qv[t][s][1].x, (int)qv[t][s][1].y,
+                                          (int)qv[t][s][1].z, (int)qv[t][s][1].w};
+                        acc[t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            a8, b8, acc[t], 0, 0, 0, 0, 0, 0);
+                    }
+                }
+            }
+            // epilogue: key = (score bits & ~mask) | index in chunk, top-2 by min / med3
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int cl = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const float nb = tnb[cl];
+                const uint32_t idx = local0 + (uint32_t)cl;
+#pragma unroll
+                for (int t = 0; t < kLpSets; ++t) {
+                    const float sc = (P == 1) ? fmaf(-2.0f, acc[t][r], nb)
+                                              : fmaf(qs2[t] * tsb[cl], acc[t][r], nb);
+                    const uint32_t key = (__float_as_uint(sc) & ~idx_mask) | idx;
+                    // sorted insertion network (keys are unique): min / med3
+                    if (K == 3) k3[t] = max(k2[t], min(k3[t], max(k1[t], key)));
+                    k2[t] = max(k1[t], min(k2[t], key));
+                    k1[t] = min(k1[t], key);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kLpSets; ++t) {
+        if (qi[t] < nA) {
+            const int64_t o = ((qi[t] * chunks + chunk) * 2 + h) * K;
+            keys[o] = k1[t];
+            keys[o + 1] = k2[t];
+            if (K == 3) keys[o + 2] = k3[t];
+        }
+    }
+}
+
+// One wavefront per query. Entries: K keys per (chunk, lane half). The 8
+// smallest kept keys are rescored in FP32 (approximate paths).
+template <int K>
+__global__ __launch_bounds__(256) void rescore_lp_kernel(
+    const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int chunks,
+    int64_t chunk_len, uint32_t idx_mask, const uint32_t* __restrict__ keys, double ratio,
+    float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
+    float* __restrict__ d2out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nA) return;
+    const int ne = chunks * 2 * K;   // <= 64
+    float sc = INFINITY;
+    int64_t j = -1;
+    if (lane < ne) {
+        const uint32_t key = keys[q * ne + lane];
+        if (key < 0x7F800000u) {
+            sc = __uint_as_float(key & ~idx_mask);
+            j = (int64_t)(lane / (2 * K)) * chunk_len + (key & idx_mask);
+        }
+    }
+    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
+    float e1 = INFINITY, e2 = INFINITY;
+    int j1 = -1, j2 = -1;
+    for (int round = 0; round < kLpRescore; ++round) {
+        float bs = sc;
+        int bl = lane;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float os = __shfl_xor(bs, off);
+            const int ol = __shfl_xor(bl, off);
+            if (os < bs || (os == bs && ol < bl)) {
+                bs = os;
+                bl = ol;
+            }
+        }
+        if (bs == INFINITY) break;
+        if (lane == bl) sc = INFINITY;
+        const int64_t jj = __shfl(j, bl);
+        best2_insert(sqdist(a0, a1, B, jj, lane), (int)jj, e1, j1, e2, j2);
+    }
+    if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
+}
+
+// ------------------------------------------------------------- BF16x3 path --
+//
+// x = hi + lo + res with hi = bf16(x), lo = bf16(x - hi) (each difference exact
+// in FP32, |res| <= 2^-16 |x|); a.b ~ hi.hi + hi.lo + lo.hi on the matrix cores
+// with FP32 accumulation starting from -|b|^2 / 2, so acc = a.b - |b|^2/2 and
+// the score |b|^2 - 2 a.b = -2 acc. Scores stay exact floats: each lane keeps
+// its top-2 (score, index) and its third-best score, which bounds everything it
+// did not keep.
+
+__device__ inline void split_bf16(float x, uint32_t& hi, uint32_t& lo, float& res)
+{
+    hi = bf16_bits(x);
+    const float r = x - __uint_as_float(hi << 16);
+    lo = bf16_bits(r);
+    res = r - __uint_as_float(lo << 16);
+}
+
+// Per row: |x|^2 (stored) and the row split into BF16 hi and lo parts (512
+// bytes: 128 hi values, then 128 lo values, the layout of the contraction's
+// LDS tile); over rows, the maxima of |x|^2, |lo|^2 and |res|^2.
+__global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict__ X, int64_t n,
+                                                         float* __restrict__ nrm,
+                                                         uint8_t* __restrict__ hl,
+                                                         uint32_t* __restrict__ maxbits)
+{
+    const int64_t row = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+    const int part = threadIdx.x % 16;
+    float s = 0.0f, sl = 0.0f, sr = 0.0f;
+    if (row < n) {
+        const float4* p = reinterpret_cast<const float4*>(X + row * 128 + part * 8);
+        const float4 a = p[0], b = p[1];
+        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint32_t h[8], l[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float res;
+            split_bf16(v[k], h[k], l[k], res);
+            const float lf = __uint_as_float(l[k] << 16);
+            s += v[k] * v[k];
+            sl += lf * lf;
+            sr += res * res;
+        }
+        *reinterpret_cast<uint4*>(hl + row * 512 + part * 16) =
+            make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+        *reinterpret_cast<uint4*>(hl + row * 512 + 256 + part * 16) =
+            make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
+    }
+    for (int off = 8; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off, 16);
+        sl += __shfl_xor(sl, off, 16);
+        sr += __shfl_xor(sr, off, 16);
+    }
+    if (row < n && part == 0) nrm[row] = s;
+    block_max_atomic(maxbits + 0, __float_as_uint(s * 1.0001f));
+    block_max_atomic(maxbits + 1, __float_as_uint(sl * 1.0001f));
+    block_max_atomic(maxbits + 2, __float_as_uint(sr * 1.0001f));
+}
+
+constexpr int kX3QB = 256;          // queries per workgroup (4 waves x 2 x 32)
+constexpr int kX3CT = 32;           // candidates per LDS tile
+constexpr int kX3Row = 512 + 16;    // LDS bytes per candidate: hi row, lo row, pad
+
+__device__ inline uint4 load_split8(const float* p, uint4& lo)
+{
+    const float4 a = reinterpret_cast<const float4*>(p)[0];
+    const float4 b = reinterpret_cast<const float4*>(p)[1];
+    const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t h[8], l[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float res;
+        split_bf16(v[k], h[k], l[k], res);
+    }
+    lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
+    return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
+// Max-ordered top-2 of acc = a.b - |b|^2/2 with indices, plus the third value;
+// ties keep the earlier (lower) index.
+__device__ inline void top2_third(float x, int j, float& b1, int& j1, float& b2, int& j2, float& b3)
+{
+    b3 = fmaxf(b3, fminf(b2, x));
+    const bool g1 = x > b1;
+    const bool g2 = x > b2;
+    b2 = g1 ? b1 : (g2 ? x : b2);
+    j2 = g1 ? j1 : (g2 ? j : j2);
+    b1 = g1 ? x : b1;
+    j1 = g1 ? j : j1;
+}
+
+__global__ __launch_bounds__(256, 2) void match_topk_x3_kernel(
+    const float* __restrict__ A, int64_t nA, const uint8_t* __restrict__ Bhl, int64_t nB,
+    const float* __restrict__ nrmB, int64_t chunk_len, int chunks, int32_t* __restrict__ cidx,
+    float* __restrict__ cscore, float* __restrict__ cthird)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kX3CT * kX3Row];
+    __shared__ __attribute__((aligned(16))) float tinit[kX3CT];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int chunk = blockIdx.y;
+    const int64_t cb = (int64_t)chunk * chunk_len;
+    const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
+
+    // queries, set t: dims [16 s + 8 h, +8) of query col as hi and lo BF16
+    uint4 qh[2][8], ql[2][8];
+    int64_t qi[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int64_t q = (int64_t)blockIdx.x * kX3QB + wave * 64 + t * 32 + col;
+        qi[t] = q;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            if (q < nA) {
+                qh[t][s] = load_split8(A + q * 128 + 16 * s + 8 * h, ql[t][s]);
+            } else {
+                qh[t][s] = make_uint4(0u, 0u, 0u, 0u);
+                ql[t][s] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    }
+    float b1[2], b2[2], b3[2];
+    int j1[2], j2[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        b1[t] = b2[t] = b3[t] = -INFINITY;
+        j1[t] = j2[t] = -1;
+    }
+
+    // a 32 x 512-byte tile of split rows: thread t moves uint4 number t + 256 k
+    uint4 pf[4];
+    auto fetch = [&](int64_t t0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int f = tid + 256 * k;
+            const int r = f >> 5, c16 = f & 31;
+            const int64_t j = t0 + r;
+            pf[k] = (j < ce) ? reinterpret_cast<const uint4*>(Bhl + j * 512)[c16]
+                             : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    if (cb < ce) fetch(cb);
+
+    for (int64_t t0 = cb; t0 < ce; t0 += kX3CT) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int f = tid + 256 * k;
+            const int r = f >> 5, c16 = f & 31;
+            *reinterpret_cast<uint4*>(&tile[r * kX3Row + c16 * 16]) = pf[k];
+        }
+        if (tid < kX3CT) tinit[tid] = (t0 + tid < ce) ? -0.5f * nrmB[t0 + tid] : -INFINITY;
+        __syncthreads();
+        if (t0 + kX3CT < ce) fetch(t0 + kX3CT);
+
+        // accumulators start at -|b|^2 / 2 of their candidate row
+        floatx16 acc[2];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 iv = *reinterpret_cast<const float4*>(&tinit[8 * g + 4 * h]);
+            acc[0][4 * g + 0] = iv.x; acc[0][4 * g + 1] = iv.y;
+            acc[0][4 * g + 2] = iv.z; acc[0][4 * g + 3] = iv.w;
+        }
+        acc[1] = acc[0];
+        const uint8_t* trow = &tile[col * kX3Row];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const uint4 bh = *reinterpret_cast<const uint4*>(trow + (16 * s + 8 * h) * 2);
+            const uint4 bl = *reinterpret_cast<const uint4*>(trow + 256 + (16 * s + 8 * h) * 2);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, bh), __builtin_bit_cast(bf16x8, qh[t][s]), acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, bl), __builtin_bit_cast(bf16x8, qh[t][s]), acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, bh), __builtin_bit_cast(bf16x8, ql[t][s]), acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int cl = 8 * (r >> 2) + 4 * h + (r & 3);
+            const int j = (int)(t0 + cl);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) top2_third(acc[t][r], j, b1[t], j1[t], b2[t], j2[t], b3[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (qi[t] < nA) {
+            const int64_t o = (qi[t] * chunks + chunk) * 4 + 2 * h;
+            cidx[o] = j1[t];
+            cidx[o + 1] = j2[t];
+            cscore[o] = -2.0f * b1[t];
+            cscore[o + 1] = -2.0f * b2[t];
+            cthird[(qi[t] * chunks + chunk) * 2 + h] = -2.0f * b3[t];
+        }
+    }
+}
+
+// One wavefront per query: certify the kept set of the BF16x3 contraction and
+// rescore it in FP32, or queue the query for the FP32 path.
+__global__ __launch_bounds__(256) void rescore_x3_kernel(
+    const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int chunks,
+    const int32_t* __restrict__ cidx, const float* __restrict__ cscore,
+    const float* __restrict__ cthird, const uint32_t* __restrict__ maxbits, double ratio,
+    float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
+    float* __restrict__ d2out, uint32_t* __restrict__ fb_count, int32_t* __restrict__ fb_list)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nA) return;
+    const int ne = chunks * 4;   // <= 64
+    float sc = INFINITY;
+    int jj = -1;
+    if (lane < ne) {
+        const int c = cidx[q * ne + lane];
+        if (c >= 0) {
+            jj = c;
+            sc = cscore[q * ne + lane];
+        }
+    }
+    float tg = (lane < 2 * chunks) ? cthird[q * 2 * chunks + lane] : INFINITY;
+    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
+    // error bound of every score, from the split errors of a and the largest
+    // of b: |(a.b)~ - a.b| <= |a_lo||b_lo| + (|a| + |a_res|)|b_res|
+    //   + |a_res|(|b| + |b_res|) + gamma (3 (|a| + |a_res|)(|b| + |b_res|) + |b|^2/2)
+    uint32_t hh, ll;
+    float r0, r1;
+    split_bf16(a0, hh, ll, r0);
+    const float l0 = __uint_as_float(ll << 16);
+    split_bf16(a1, hh, ll, r1);
+    const float l1 = __uint_as_float(ll << 16);
+    const float an = sqrtf(wave_sum(a0 * a0 + a1 * a1));
+    const float aln = sqrtf(wave_sum(l0 * l0 + l1 * l1)) * 1.0001f;
+    const float arn = sqrtf(wave_sum(r0 * r0 + r1 * r1)) * 1.0001f;
+    const float bn2 = __uint_as_float(maxbits[0]);
+    const float bn = sqrtf(bn2), bln = sqrtf(__uint_as_float(maxbits[1]));
+    const float brn = sqrtf(__uint_as_float(maxbits[2]));
+    const float gamma = 385.0f * 5.9604645e-8f;   // FP32 additions along one accumulator chain
+    const float dot_err = aln * bln + (an + arn) * brn + arn * (bn + brn)
+                          + gamma * (3.0f * (an + arn) * (bn + brn) + 0.5f * bn2);
+    // score = -2 acc; |b|^2 itself carries the FP32 error of a 128-term sum
+    const float E = 2.02f * dot_err + 1e-5f * bn2 + 1e-7f;
+    // T: best score any group may have left behind (its third best)
+    float m1 = sc, m2 = INFINITY;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        tg = fminf(tg, __shfl_xor(tg, off));
+        const float o1 = __shfl_xor(m1, off), o2 = __shfl_xor(m2, off);
+        const float n1 = fminf(m1, o1);
+        m2 = fminf(fmaxf(m1, o1), fminf(m2, o2));
+        m1 = n1;
+    }
+    const float U2 = m2 + E;
+    if (!(tg - E > U2)) {
+        if (lane == 0) {
+            const uint32_t pos = atomicAdd(fb_count, 1u);
+            fb_list[pos] = (int32_t)q;
+        }
+        return;
+    }
+    float e1 = INFINITY, e2 = INFINITY;
+    int j1 = -1, j2 = -1;
+    uint64_t todo = __ballot(jj >= 0 && sc - E <= U2);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int j = __shfl(jj, l);
+        best2_insert(sqdist(a0, a1, B, j, lane), j, e1, j1, e2, j2);
+    }
+    if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
+}
+
+// Per-call scalars of the quantised paths: [0] = C as float, [1] = max |a|^2
+// bits, [2] = max |b|^2 bits. C > (1 + 2 err)(|a|^2 + |b|^2) keeps every score
+// |b|^2 + C - 2 (a.b)~ positive, so that float bits order like values.
+__global__ void lp_scalars_kernel(float* scal, float dot_err)
+{
+    const float maxa2 = __uint_as_float(reinterpret_cast<const uint32_t*>(scal)[1]);
+    const float maxb2 = __uint_as_float(reinterpret_cast<const uint32_t*>(scal)[2]);
+    scal[0] = (1.0f + 2.0f * dot_err) * (maxa2 + maxb2) + 1.0f;
+}
+
+// ------------------------------------------------------------------ layout --
+
+struct WsF32 {
     size_t nrm, cidx, cscore, total;
 };
 
-WsLayout ws_layout(int64_t nA, int64_t nB, const MatchPlan& p)
+WsF32 ws_f32(int64_t nA, int64_t nB, const MatchPlan& p)
 {
-    WsLayout w;
+    WsF32 w;
     w.nrm = 0;
     w.cidx = align_up((size_t)nB * 4, 256);
     const size_t nc = (size_t)nA * (size_t)p.chunks * kKeep;
@@ -239,57 +901,257 @@ WsLayout ws_layout(int64_t nA, int64_t nB, const MatchPlan& p)
     return w;
 }
 
+// quantised paths (precision 1, 2)
+struct WsLp {
+    size_t scal, aq, bq, sa, sb, keys, nrm, total;
+};
+
+WsLp ws_lp(int64_t nA, int64_t nB, int precision, const MatchPlan& p)
+{
+    const size_t rb = (precision == 1) ? 256 : 128;
+    const int keep = (precision == 1) ? kLpKeepBf16 : kLpKeepFp8;
+    WsLp w;
+    w.scal = 0;
+    w.aq = 256;
+    w.bq = w.aq + align_up((size_t)nA * rb, 256);
+    w.sa = w.bq + align_up((size_t)nB * rb, 256);
+    w.sb = w.sa + align_up((size_t)nA * 4, 256);
+    w.keys = w.sb + align_up((size_t)nB * 4, 256);
+    w.nrm = w.keys + align_up((size_t)nA * p.chunks * 2 * keep * 4, 256);
+    w.total = w.nrm + align_up((size_t)nB * 4, 256);
+    return w;
+}
+
+// split path (precision 3): counters, candidate lists, thirds, fallback list,
+// then the FP32 path's own workspace for the fallback
+struct WsX3 {
+    size_t cnt, bhl, cidx, cscore, cthird, fb, f32, total;
+};
+
+WsX3 ws_x3(int64_t nA, int64_t nB, const MatchPlan& p, const MatchPlan& pf)
+{
+    WsX3 w;
+    w.cnt = 0;
+    const size_t nc = (size_t)nA * (size_t)p.chunks * 4;
+    w.bhl = 256;
+    w.cidx = w.bhl + align_up((size_t)nB * 512, 256);
+    w.cscore = w.cidx + align_up(nc * 4, 256);
+    w.cthird = w.cscore + align_up(nc * 4, 256);
+    w.fb = w.cthird + align_up((size_t)nA * p.chunks * 2 * 4, 256);
+    w.f32 = w.fb + align_up((size_t)nA * 4, 256);
+    w.total = w.f32 + ws_f32(nA, nB, pf).total;
+    return w;
+}
+
+
+MatchPlan plan_chunks(int64_t nA, int64_t nB, int qb_size, int tile, int max_chunks, int req)
+{
+    MatchPlan p;
+    int chunks = req;
+    if (chunks <= 0) {
+        // about two resident workgroups per compute unit (256 CUs): pick the
+        // chunk count whose grid comes closest to a whole number of rounds
+        const int64_t qblocks = (nA + qb_size - 1) / qb_size;
+        chunks = 1;
+        double best = -1.0;
+        for (int c = 1; c <= max_chunks; ++c) {
+            const double rounds = (double)qblocks * c / 512.0;
+            const double eff = rounds / std::ceil(rounds);
+            if (eff > best + 0.02) {   // prefer full rounds, then fewer chunks
+                best = eff;
+                chunks = c;
+            }
+        }
+    }
+    if (chunks > max_chunks) chunks = max_chunks;
+    const int64_t tiles = (nB + tile - 1) / tile;
+    if (tiles > 0 && chunks > tiles) chunks = (int)tiles;
+    if (chunks < 1) chunks = 1;
+    p.chunks = chunks;
+    p.chunk_len = ((tiles + chunks - 1) / chunks) * tile;
+    return p;
+}
+
+uint32_t idx_mask_for(int64_t chunk_len)
+{
+    uint32_t m = 1;
+    while ((int64_t)m < chunk_len) m <<= 1;
+    return m - 1;
+}
+
+MatchPlan plan_fp32(int64_t nA, int64_t nB, int req)
+{
+    return plan_chunks(nA, nB, kQB, kCT, 16, req);
+}
+
+// The FP32 re-match of uncertified queries: usually few queries, so the
+// candidate range is split finely (the rescore merges up to 256 entries).
+MatchPlan plan_fallback(int64_t nA, int64_t nB)
+{
+    return plan_chunks(nA, nB, kQB, kCT, 64, 64);
+}
+
 }  // namespace
 
 MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp)
 {
-    MatchPlan p;
-    int chunks = mp->b_chunks;
-    if (chunks <= 0) {
-        // aim for about two resident workgroups per compute unit (256 CUs)
-        const int64_t qblocks = (nA + kQB - 1) / kQB;
-        chunks = (int)((512 + qblocks - 1) / (qblocks > 0 ? qblocks : 1));
-        if (chunks < 1) chunks = 1;
+    switch (mp->precision) {
+    case 0: return plan_fp32(nA, nB, mp->b_chunks);
+    case 3: return plan_chunks(nA, nB, kX3QB, kX3CT, 16, mp->b_chunks);
+    default: {
+        // the rescore wavefront holds chunks x 2 lane halves x K keys
+        const int keep = (mp->precision == 1) ? kLpKeepBf16 : kLpKeepFp8;
+        return plan_chunks(nA, nB, kLpQB, kLpCT, 64 / (2 * keep), mp->b_chunks);
     }
-    if (chunks > 16) chunks = 16;
-    const int64_t tiles = (nB + kCT - 1) / kCT;
-    if (tiles > 0 && chunks > tiles) chunks = (int)tiles;
-    if (chunks < 1) chunks = 1;
-    p.chunks = chunks;
-    p.chunk_len = ((tiles + chunks - 1) / chunks) * kCT;
-    return p;
+    }
 }
 
 size_t match_workspace_bytes(int64_t nA, int64_t nB, const lpsift_match_params* mp)
 {
-    return ws_layout(nA, nB, plan_match(nA, nB, mp)).total;
+    const MatchPlan p = plan_match(nA, nB, mp);
+    switch (mp->precision) {
+    case 0: return ws_f32(nA, nB, p).total;
+    case 3: return ws_x3(nA, nB, p, plan_fallback(nA, nB)).total;
+    default: {
+        // an empty candidate set is handled by the FP32 kernels
+        const size_t a = ws_lp(nA, nB, mp->precision, p).total;
+        const size_t b = ws_f32(nA, nB, plan_fp32(nA, nB, 0)).total;
+        return a > b ? a : b;
+    }
+    }
 }
+
+namespace {
+
+int launch_f32(const float* A, int64_t nA, const float* B, int64_t nB, const MatchPlan& pf,
+               const lpsift_match_params* mp, char* base, int32_t* match, float* d1, float* d2,
+               hipStream_t stream)
+{
+    const WsF32 L = ws_f32(nA, nB, pf);
+    float* nrm = reinterpret_cast<float*>(base + L.nrm);
+    int32_t* cidx = reinterpret_cast<int32_t*>(base + L.cidx);
+    float* cscore = reinterpret_cast<float*>(base + L.cscore);
+    if (nB > 0) {
+        hipLaunchKernelGGL(sqnorm_kernel, dim3((unsigned)((nB + 15) / 16)), dim3(256), 0, stream,
+                           B, nB, nrm, (uint32_t*)nullptr);
+        const dim3 grid((unsigned)((nA + kQB - 1) / kQB), (unsigned)pf.chunks);
+        hipLaunchKernelGGL(match_topk_f32_kernel, grid, dim3(256), 0, stream, A, nA, B, nB, nrm,
+                           pf.chunk_len, pf.chunks, (const int32_t*)nullptr,
+                           (const uint32_t*)nullptr, cidx, cscore);
+    }
+    hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((nA + 3) / 4)), dim3(256), 0, stream, A,
+                       nA, B, (nB > 0) ? pf.chunks : 0, (const int32_t*)nullptr,
+                       (const uint32_t*)nullptr, cidx, cscore, mp->ratio, mp->abs_thresh, match,
+                       d1, d2);
+    return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
+}
+
+}  // namespace
 
 int launch_match(const float* A, int64_t nA, const float* B, int64_t nB,
                  const lpsift_match_params* mp, void* ws, int32_t* match, float* d1, float* d2,
                  hipStream_t stream)
 {
     if (nA == 0) return LPSIFT_OK;
-    const MatchPlan p = plan_match(nA, nB, mp);
-    const WsLayout L = ws_layout(nA, nB, p);
     char* base = static_cast<char*>(ws);
-    float* nrm = reinterpret_cast<float*>(base + L.nrm);
-    int32_t* cidx = reinterpret_cast<int32_t*>(base + L.cidx);
-    float* cscore = reinterpret_cast<float*>(base + L.cscore);
-    if (nB > 0) {
-        hipLaunchKernelGGL(sqnorm_kernel, dim3((unsigned)((nB + 15) / 16)), dim3(256), 0, stream,
-                           B, nB, nrm);
-        if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
-        const dim3 grid((unsigned)((nA + kQB - 1) / kQB), (unsigned)p.chunks);
-        hipLaunchKernelGGL(match_topk_f32_kernel, grid, dim3(256), 0, stream, A, nA, B, nB, nrm,
-                           p.chunk_len, p.chunks, cidx, cscore);
-        if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+
+    if (mp->precision == 0 || nB == 0) {
+        const MatchPlan pf = plan_fp32(nA, nB, mp->precision == 0 ? mp->b_chunks : 0);
+        const int st = launch_f32(A, nA, B, nB, pf, mp, base, match, d1, d2, stream);
+        if (st != LPSIFT_OK) return st;
+        // counters are not used here: report zero re-matched queries
+        if (mp->stats) {
+            hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream,
+                               static_cast<uint32_t*>(mp->stats), 1);
+        }
+        return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
     }
-    const int chunks = (nB > 0) ? p.chunks : 0;
-    hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((nA + 3) / 4)), dim3(256), 0, stream, A, nA,
-                       B, chunks, cidx, cscore, mp->ratio, mp->abs_thresh, match, d1, d2);
-    if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
-    return LPSIFT_OK;
+
+    const MatchPlan p = plan_match(nA, nB, mp);
+    const dim3 gr((unsigned)((nA + 3) / 4));
+
+    if (mp->precision == 3) {
+        const MatchPlan pf = plan_fallback(nA, nB);
+        const WsX3 L = ws_x3(nA, nB, p, pf);
+        const WsF32 F = ws_f32(nA, nB, pf);
+        uint32_t* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);   // [0] fallbacks, [1..3] maxima
+        int32_t* cidx = reinterpret_cast<int32_t*>(base + L.cidx);
+        float* cscore = reinterpret_cast<float*>(base + L.cscore);
+        float* cthird = reinterpret_cast<float*>(base + L.cthird);
+        int32_t* fb = reinterpret_cast<int32_t*>(base + L.fb);
+        char* fbase = base + L.f32;
+        float* nrm = reinterpret_cast<float*>(fbase + F.nrm);
+        int32_t* fidx = reinterpret_cast<int32_t*>(fbase + F.cidx);
+        float* fscore = reinterpret_cast<float*>(fbase + F.cscore);
+
+        uint8_t* bhl = reinterpret_cast<uint8_t*>(base + L.bhl);
+        hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, 4);
+        hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((nB + 15) / 16)), dim3(256), 0,
+                           stream, B, nB, nrm, bhl, cnt + 1);
+        const dim3 grid((unsigned)((nA + kX3QB - 1) / kX3QB), (unsigned)p.chunks);
+        hipLaunchKernelGGL(match_topk_x3_kernel, grid, dim3(256), 0, stream, A, nA, bhl, nB, nrm,
+                           p.chunk_len, p.chunks, cidx, cscore, cthird);
+        hipLaunchKernelGGL(rescore_x3_kernel, gr, dim3(256), 0, stream, A, nA, B, p.chunks, cidx,
+                           cscore, cthird, (const uint32_t*)(cnt + 1), mp->ratio, mp->abs_thresh,
+                           match, d1, d2, cnt, fb);
+        // queries the bound could not certify: FP32 path over the device-side list
+        const dim3 gf((unsigned)((nA + kQB - 1) / kQB), (unsigned)pf.chunks);
+        hipLaunchKernelGGL(match_topk_f32_kernel, gf, dim3(256), 0, stream, A, nA, B, nB, nrm,
+                           pf.chunk_len, pf.chunks, fb, cnt, fidx, fscore);
+        hipLaunchKernelGGL(rescore_kernel, gr, dim3(256), 0, stream, A, nA, B, pf.chunks, fb, cnt,
+                           fidx, fscore, mp->ratio, mp->abs_thresh, match, d1, d2);
+        if (mp->stats) {
+            hipLaunchKernelGGL(copy_u32_kernel, dim3(1), dim3(1), 0, stream,
+                               static_cast<uint32_t*>(mp->stats), cnt);
+        }
+        return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
+    }
+
+    // quantised approximate paths
+    const WsLp L = ws_lp(nA, nB, mp->precision, p);
+    float* scal = reinterpret_cast<float*>(base + L.scal);
+    uint32_t* counters = reinterpret_cast<uint32_t*>(scal);   // [1], [2] max bits
+    uint8_t* aq = reinterpret_cast<uint8_t*>(base + L.aq);
+    uint8_t* bq = reinterpret_cast<uint8_t*>(base + L.bq);
+    float* sa = reinterpret_cast<float*>(base + L.sa);
+    float* sb = reinterpret_cast<float*>(base + L.sb);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(base + L.keys);
+    float* nrm = reinterpret_cast<float*>(base + L.nrm);
+    const uint32_t mask = idx_mask_for(p.chunk_len);
+    const dim3 grid((unsigned)((nA + kLpQB - 1) / kLpQB), (unsigned)p.chunks);
+    const dim3 gq((unsigned)((nA + 15) / 16)), gqb((unsigned)((nB + 15) / 16));
+
+    hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream, counters, 4);
+    hipLaunchKernelGGL(sqnorm_kernel, gq, dim3(256), 0, stream, A, nA, (float*)nullptr, counters + 1);
+    hipLaunchKernelGGL(sqnorm_kernel, gqb, dim3(256), 0, stream, B, nB, nrm, counters + 2);
+    if (mp->precision == 1) {
+        hipLaunchKernelGGL(quantize_kernel<1>, gq, dim3(256), 0, stream, A, nA, aq, sa,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(quantize_kernel<1>, gqb, dim3(256), 0, stream, B, nB, bq, sb,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(lp_scalars_kernel, dim3(1), dim3(1), 0, stream, scal, kBf16DotErr);
+        hipLaunchKernelGGL((match_topk_lp_kernel<1, kLpKeepBf16>), grid, dim3(256), 0, stream, aq,
+                           sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
+        hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepBf16>), gr, dim3(256), 0, stream, A, nA, B,
+                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, match,
+                           d1, d2);
+    } else {
+        hipLaunchKernelGGL(quantize_kernel<2>, gq, dim3(256), 0, stream, A, nA, aq, sa,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(quantize_kernel<2>, gqb, dim3(256), 0, stream, B, nB, bq, sb,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(lp_scalars_kernel, dim3(1), dim3(1), 0, stream, scal, 0.13f);
+        hipLaunchKernelGGL((match_topk_lp_kernel<2, kLpKeepFp8>), grid, dim3(256), 0, stream, aq,
+                           sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
+        hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepFp8>), gr, dim3(256), 0, stream, A, nA, B,
+                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, match,
+                           d1, d2);
+    }
+    if (mp->stats) {
+        hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream,
+                           static_cast<uint32_t*>(mp->stats), 1);
+    }
+    return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
 }
 
 }  // namespace lpsift

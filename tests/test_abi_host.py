@@ -147,7 +147,11 @@ def test_match_validation_and_workspace(lib):
     assert call(mp, ws=0x100000 + 8) == lp.LPSIFT_EINVAL
     for bad in (lp.match_params(ratio=0.0), lp.match_params(ratio=math.nan),
                 lp.match_params(abs_thresh=math.nan), lp.match_params(abs_thresh=-1.0),
-                lp.match_params(b_chunks=17), lp.match_params(precision=3)):
+                lp.match_params(b_chunks=17), lp.match_params(precision=4)):
         assert call(bad) == lp.LPSIFT_EINVAL
-    assert call(lp.match_params(precision=1)) == lp.LPSIFT_EUNSUPPORTED
+    # low-precision paths need more workspace (quantised copies, keys, FP32 fallback)
+    for prec in (1, 2, 3):
+        mlp = lp.match_params(precision=prec)
+        assert lp.match_workspace_size(nA, nB, mlp) > need
+        assert call(mlp) == lp.LPSIFT_ECAPACITY
     assert lp.match_workspace_size([10], [0], mp) >= 0

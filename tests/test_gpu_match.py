@@ -26,6 +26,7 @@ def run_match(gpu, A, B, **kw):
     ta = torch.from_numpy(np.ascontiguousarray(A, np.float32)).to(gpu)
     tb = torch.from_numpy(np.ascontiguousarray(B, np.float32)).to(gpu)
     r = lp.match([ta], [tb], **kw)[0]
+    torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in r.items()}
 
 
