@@ -102,8 +102,8 @@ typedef struct lpsift_keypoints {
  *                  precision 0, so the lists equal precision 0's.
  *  b_chunks    candidate-range split of the contraction (0 = automatic, <= 16)
  *  stats       optional device pointer to one uint32: after the call (stream
- *              order) it holds the number of queries of the last pair that
- *              precision 3 re-matched with precision 0 (0 otherwise) */
+ *              order) it holds the number of queries, summed over all pairs,
+ *              that precision 3 re-matched with precision 0 (0 otherwise) */
 typedef struct lpsift_match_params {
     double ratio;
     float abs_thresh;
@@ -181,6 +181,10 @@ size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t
  *  descA, descB  host arrays of n_pairs device pointers to float[n][128]
  *  nA, nB        host arrays of n_pairs counts (nA >= 0, nB >= 0)
  *  match, d1, d2 host arrays of n_pairs device pointers to int32/float[nA]
+ * Precisions 0 and 3 run up to 16 pairs per kernel launch, and the norms of a
+ * registered set that several pairs share (same pointer and count) are
+ * computed once per call: all-pairs matching of N images costs a handful of
+ * launches. Outputs must not overlap any input or each other.
  * Errors: EINVAL (null pointer, negative count, descriptor pointer not 16-byte
  * aligned, workspace not 256-byte aligned, bad ratio/abs_thresh/precision),
  * ECAPACITY (workspace), EHIP. */

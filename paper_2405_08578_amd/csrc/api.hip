@@ -3,6 +3,7 @@
 // memory, synchronises, throws or aborts.
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 
@@ -202,14 +203,13 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
     if (sp != LPSIFT_OK) return sp;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
     if (ws_bytes < lpsift_match_workspace_size(nA, nB, n_pairs, mp)) return LPSIFT_ECAPACITY;
+    std::vector<MatchPairIO> io(n_pairs);
     char* ws = static_cast<char*>(workspace);
     for (int i = 0; i < n_pairs; ++i) {
-        const int st = launch_match(descA[i], nA[i], descB[i], nB[i], mp, ws, match[i], d1[i],
-                                    d2[i], static_cast<hipStream_t>(stream));
-        if (st != LPSIFT_OK) return st;
+        io[i] = MatchPairIO{descA[i], nA[i], descB[i], nB[i], ws, match[i], d1[i], d2[i]};
         ws += align_up(match_workspace_bytes(nA[i], nB[i], mp), 256);
     }
-    return LPSIFT_OK;
+    return launch_match_pairs(io.data(), n_pairs, mp, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -31,7 +31,7 @@ namespace {
 constexpr float kTwoPiInv = 0.15915494309189535f;  // 1 / (2 pi)
 
 // Images per launch (keeps the by-value kernel arguments small).
-constexpr int kDescBatch = 8;
+constexpr int kDescBatch = kMaxBatch;
 
 // ---------------------------------------------------------------- tables --
 

@@ -78,8 +78,22 @@ struct MatchPlan {
 };
 MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp);
 size_t match_workspace_bytes(int64_t nA, int64_t nB, const lpsift_match_params* mp);
-int launch_match(const float* A, int64_t nA, const float* B, int64_t nB,
-                 const lpsift_match_params* mp, void* ws, int32_t* match, float* d1,
-                 float* d2, hipStream_t s);
+
+// One pair of a match call: descriptor sets, its 256-byte aligned workspace
+// slice of match_workspace_bytes(nA, nB), and its outputs.
+struct MatchPairIO {
+    const float* A;
+    int64_t nA;
+    const float* B;
+    int64_t nB;
+    void* ws;
+    int32_t* match;
+    float* d1;
+    float* d2;
+};
+// All pairs of a call; the FP32 and split paths batch up to 16 pairs per
+// launch and compute the norms of a candidate set shared by several pairs once.
+int launch_match_pairs(const MatchPairIO* pairs, int n, const lpsift_match_params* mp,
+                       hipStream_t s);
 
 }  // namespace lpsift

@@ -41,6 +41,8 @@
 // than 2E, the true two nearest are among the kept ones and FP32 rescoring of
 // those is exact. Other queries go to a device-side list matched by the FP32
 // path. The lists equal the FP32 path's.
+#include <vector>
+
 #include "internal.h"
 
 namespace lpsift {
@@ -68,8 +70,6 @@ __global__ void init_counters_kernel(uint32_t* c, int n)
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
-__global__ void copy_u32_kernel(uint32_t* dst, const uint32_t* src) { *dst = *src; }
-
 // Maximum of v over the 256-thread workgroup, merged into *dst with one
 // atomic per workgroup (v: bits of non-negative floats, which order like
 // unsigned integers).
@@ -83,13 +83,13 @@ __device__ inline void block_max_atomic(uint32_t* dst, uint32_t v)
     __syncthreads();
 }
 
-// |x|^2 of every row (optional output) and the maximum over rows, as the bit
-// pattern of a non-negative float (bits order like values), 16 lanes per row.
-__global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X, int64_t n,
-                                                     float* __restrict__ out,
-                                                     uint32_t* __restrict__ maxbits)
+// |x|^2 of the 16 rows of block blk (optional output) and the maximum over
+// rows, as the bit pattern of a non-negative float (bits order like values),
+// 16 lanes per row.
+__device__ inline void sqnorm_rows(const float* __restrict__ X, int64_t n, int64_t blk,
+                                   float* __restrict__ out, uint32_t* __restrict__ maxbits)
 {
-    const int64_t row = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+    const int64_t row = blk * 16 + threadIdx.x / 16;
     const int part = threadIdx.x % 16;
     float s = 0.0f;
     if (row < n) {
@@ -100,6 +100,13 @@ __global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X
     for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
     if (row < n && part == 0 && out) out[row] = s;
     if (maxbits) block_max_atomic(maxbits, __float_as_uint(s));   // rows beyond n have s = 0
+}
+
+__global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X, int64_t n,
+                                                     float* __restrict__ out,
+                                                     uint32_t* __restrict__ maxbits)
+{
+    sqnorm_rows(X, n, blockIdx.x, out, maxbits);
 }
 
 // ---------------------------------------------------------------- FP32 path --
@@ -116,26 +123,25 @@ __device__ inline void top2_push(float s, int j, float& s1, int& j1, float& s2, 
     j1 = lt1 ? j : j1;
 }
 
-// qlist/qcount (optional): match only the queries qlist[0 .. *qcount); results
-// for list entry i are stored at position i.
-__global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(
-    const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int64_t nB,
-    const float* __restrict__ nrmB, int64_t chunk_len, int chunks,
-    const int32_t* __restrict__ qlist, const uint32_t* __restrict__ qcount,
-    int32_t* __restrict__ cidx, float* __restrict__ cscore)
+// One (query block, chunk) work item of the FP32 contraction. nq: number of
+// queries; qlist (optional) maps list entry i to its query row, results for
+// entry i are stored at position i.
+__device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
+                                     const int32_t* __restrict__ qlist,
+                                     const float* __restrict__ B, int64_t nB,
+                                     const float* __restrict__ nrmB, int64_t chunk_len, int chunks,
+                                     int32_t* __restrict__ cidx, float* __restrict__ cscore,
+                                     int64_t qblk, int chunk)
 {
     __shared__ __attribute__((aligned(16))) float tile[kCT * kRow];
     __shared__ float tnrm[kCT];
-    const int64_t nq = qlist ? (int64_t)*qcount : nA;
-    if ((int64_t)blockIdx.x * kQB >= nq) return;   // whole workgroup
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t i0 = (int64_t)blockIdx.x * kQB + wave * 64 + col;
+    const int64_t i0 = qblk * kQB + wave * 64 + col;
     const int64_t i1 = i0 + 32;
     const int64_t q0 = (i0 < nq) ? (qlist ? qlist[i0] : i0) : -1;
     const int64_t q1 = (i1 < nq) ? (qlist ? qlist[i1] : i1) : -1;
-    const int chunk = blockIdx.y;
     const int64_t cb = (int64_t)chunk * chunk_len;
     const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
 
@@ -264,18 +270,14 @@ __device__ inline void write_result(int64_t q, float e1, int j1, float e2, doubl
 // One wavefront per query: keep the 4 best candidates by contraction score
 // (chunks x 4 entries, up to 256: 4 per lane), recompute their distances
 // directly, then the ratio test.
-__global__ __launch_bounds__(256) void rescore_kernel(
-    const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int chunks,
-    const int32_t* __restrict__ qlist, const uint32_t* __restrict__ qcount,
-    const int32_t* __restrict__ cidx, const float* __restrict__ cscore, double ratio,
-    float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
-    float* __restrict__ d2out)
+__device__ inline void rescore_f32_query(const float* __restrict__ A, const float* __restrict__ B,
+                                         int chunks, int64_t i, int64_t q,
+                                         const int32_t* __restrict__ cidx,
+                                         const float* __restrict__ cscore, double ratio,
+                                         float abs_thresh, int32_t* __restrict__ match,
+                                         float* __restrict__ d1out, float* __restrict__ d2out)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nq = qlist ? (int64_t)*qcount : nA;
-    if (i >= nq) return;
-    const int64_t q = qlist ? qlist[i] : i;
     const int nc = chunks * kKeep;   // <= 256
     float sc[4];
     int id[4];
@@ -620,12 +622,11 @@ __device__ inline void split_bf16(float x, uint32_t& hi, uint32_t& lo, float& re
 // Per row: |x|^2 (stored) and the row split into BF16 hi and lo parts (512
 // bytes: 128 hi values, then 128 lo values, the layout of the contraction's
 // LDS tile); over rows, the maxima of |x|^2, |lo|^2 and |res|^2.
-__global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict__ X, int64_t n,
-                                                         float* __restrict__ nrm,
-                                                         uint8_t* __restrict__ hl,
-                                                         uint32_t* __restrict__ maxbits)
+__device__ inline void split_rows(const float* __restrict__ X, int64_t n, int64_t blk,
+                                  float* __restrict__ nrm, uint8_t* __restrict__ hl,
+                                  uint32_t* __restrict__ maxbits)
 {
-    const int64_t row = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+    const int64_t row = blk * 16 + threadIdx.x / 16;
     const int part = threadIdx.x % 16;
     float s = 0.0f, sl = 0.0f, sr = 0.0f;
     if (row < n) {
@@ -690,17 +691,17 @@ __device__ inline void top2_third(float x, int j, float& b1, int& j1, float& b2,
     j1 = g1 ? j : j1;
 }
 
-__global__ __launch_bounds__(256, 2) void match_topk_x3_kernel(
-    const float* __restrict__ A, int64_t nA, const uint8_t* __restrict__ Bhl, int64_t nB,
-    const float* __restrict__ nrmB, int64_t chunk_len, int chunks, int32_t* __restrict__ cidx,
-    float* __restrict__ cscore, float* __restrict__ cthird)
+__device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
+                                    const uint8_t* __restrict__ Bhl, int64_t nB,
+                                    const float* __restrict__ nrmB, int64_t chunk_len, int chunks,
+                                    int32_t* __restrict__ cidx, float* __restrict__ cscore,
+                                    float* __restrict__ cthird, int64_t qblk, int chunk)
 {
     __shared__ __attribute__((aligned(16))) uint8_t tile[kX3CT * kX3Row];
     __shared__ __attribute__((aligned(16))) float tinit[kX3CT];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int chunk = blockIdx.y;
     const int64_t cb = (int64_t)chunk * chunk_len;
     const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
 
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_x3_kernel(
     int64_t qi[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        const int64_t q = (int64_t)blockIdx.x * kX3QB + wave * 64 + t * 32 + col;
+        const int64_t q = qblk * kX3QB + wave * 64 + t * 32 + col;
         qi[t] = q;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -802,16 +803,14 @@ __global__ __launch_bounds__(256, 2) void match_topk_x3_kernel(
 
 // One wavefront per query: certify the kept set of the BF16x3 contraction and
 // rescore it in FP32, or queue the query for the FP32 path.
-__global__ __launch_bounds__(256) void rescore_x3_kernel(
-    const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int chunks,
+__device__ inline void rescore_x3_query(
+    const float* __restrict__ A, const float* __restrict__ B, int chunks, int64_t q,
     const int32_t* __restrict__ cidx, const float* __restrict__ cscore,
     const float* __restrict__ cthird, const uint32_t* __restrict__ maxbits, double ratio,
     float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
     float* __restrict__ d2out, uint32_t* __restrict__ fb_count, int32_t* __restrict__ fb_list)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nA) return;
     const int ne = chunks * 4;   // <= 64
     float sc = INFINITY;
     int jj = -1;
@@ -882,6 +881,234 @@ __global__ void lp_scalars_kernel(float* scal, float dot_err)
     const float maxa2 = __uint_as_float(reinterpret_cast<const uint32_t*>(scal)[1]);
     const float maxb2 = __uint_as_float(reinterpret_cast<const uint32_t*>(scal)[2]);
     scal[0] = (1.0f + 2.0f * dot_err) * (maxa2 + maxb2) + 1.0f;
+}
+
+// ------------------------------------------------------------- batched launches --
+//
+// One launch serves up to kPairs pairs: each kernel takes a table of per-pair
+// jobs by value and walks a flat range of work items, item `it` belonging to
+// the first job whose cumulative item count exceeds it. Item counts may depend
+// on device-side query counts (the FP32 re-match of uncertified queries), so
+// they are evaluated inside the kernel; such launches use a grid smaller than
+// the largest possible item range and stride over it.
+
+constexpr int kPairs = 16;
+
+// Job k of batch b that item `it` belongs to (-1 past the end) and the item's
+// index within that job. items(job) must be uniform across the workgroup.
+template <class Batch, class Items>
+__device__ inline int find_job(const Batch& b, int64_t it, Items items, int64_t& local)
+{
+    int64_t base = 0;
+    for (int k = 0; k < b.n; ++k) {
+        const int64_t c = items(b.j[k]);
+        if (it < base + c) {
+            local = it - base;
+            return k;
+        }
+        base += c;
+    }
+    return -1;
+}
+
+// Per distinct candidate set: |b|^2 of every row, and for the split path the
+// BF16 hi/lo rows and the row maxima.
+struct RowsJob {
+    const float* X;
+    float* nrm;
+    uint8_t* hl;          // split rows (split path), else null
+    uint32_t* maxbits;    // split path: maxima of |x|^2, |lo|^2, |res|^2
+    int64_t n;
+};
+struct RowsBatch {
+    int32_t n;
+    RowsJob j[kPairs];
+};
+
+__global__ __launch_bounds__(256) void rows_kernel(const RowsBatch b)
+{
+    int64_t blk;
+    const int k = find_job(b, (int64_t)blockIdx.x,
+                           [](const RowsJob& J) { return (J.n + 15) / 16; }, blk);
+    if (k < 0) return;
+    const RowsJob& J = b.j[k];
+    if (J.hl)
+        split_rows(J.X, J.n, blk, J.nrm, J.hl, J.maxbits);
+    else
+        sqnorm_rows(J.X, J.n, blk, J.nrm, nullptr);
+}
+
+// FP32 contraction with top-2 per lane. Items of a job are (chunk, query
+// block) with the query block fastest, so workgroups running together share
+// a candidate chunk. With qlist set, the job's queries are the first *qcount
+// entries of that list.
+struct F32Job {
+    const float* A;
+    const int32_t* qlist;
+    const uint32_t* qcount;
+    const float* B;
+    const float* nrm;
+    int32_t* cidx;
+    float* cscore;
+    int64_t nq;           // queries (without a list), else the list's capacity
+    int64_t nB;
+    int64_t chunk_len;
+    int32_t chunks;
+};
+struct F32Batch {
+    int32_t n;
+    F32Job j[kPairs];
+};
+
+__device__ inline int64_t f32_queries(const F32Job& J)
+{
+    return J.qlist ? (int64_t)*J.qcount : J.nq;
+}
+
+__global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(const F32Batch b)
+{
+    auto items = [](const F32Job& J) { return (f32_queries(J) + kQB - 1) / kQB * J.chunks; };
+    for (int64_t it = blockIdx.x;; it += gridDim.x) {
+        int64_t local;
+        const int k = find_job(b, it, items, local);
+        if (k < 0) return;
+        const F32Job& J = b.j[k];
+        const int64_t nq = f32_queries(J);
+        const int64_t qblocks = (nq + kQB - 1) / kQB;
+        const int chunk = (int)(local / qblocks);
+        topk_f32_item(J.A, nq, J.qlist, J.B, J.nB, J.nrm, J.chunk_len, J.chunks, J.cidx, J.cscore,
+                      local - chunk * qblocks, chunk);
+        __syncthreads();   // the LDS tile is reused by the next item
+    }
+}
+
+// FP32 rescore, one wavefront per query (list entry). chunks = 0: no
+// candidates (an empty candidate set), every query is rejected.
+struct RescoreF32Job {
+    const float* A;
+    const float* B;
+    const int32_t* qlist;
+    const uint32_t* qcount;
+    const int32_t* cidx;
+    const float* cscore;
+    int32_t* match;
+    float* d1;
+    float* d2;
+    int64_t nq;
+    int32_t chunks;
+};
+struct RescoreF32Batch {
+    int32_t n;
+    double ratio;
+    float abs_thresh;
+    RescoreF32Job j[kPairs];
+};
+
+__global__ __launch_bounds__(256) void rescore_f32_kernel(const RescoreF32Batch b)
+{
+    auto items = [](const RescoreF32Job& J) {
+        return ((J.qlist ? (int64_t)*J.qcount : J.nq) + 3) / 4;
+    };
+    for (int64_t it = blockIdx.x;; it += gridDim.x) {
+        int64_t local;
+        const int k = find_job(b, it, items, local);
+        if (k < 0) return;
+        const RescoreF32Job& J = b.j[k];
+        const int64_t nq = J.qlist ? (int64_t)*J.qcount : J.nq;
+        const int64_t i = local * 4 + (threadIdx.x >> 6);
+        if (i < nq)
+            rescore_f32_query(J.A, J.B, J.chunks, i, J.qlist ? J.qlist[i] : i, J.cidx, J.cscore,
+                              b.ratio, b.abs_thresh, J.match, J.d1, J.d2);
+    }
+}
+
+// Split-BF16 contraction, one item per (chunk, query block).
+struct X3Job {
+    const float* A;
+    const uint8_t* Bhl;
+    const float* nrm;
+    int32_t* cidx;
+    float* cscore;
+    float* cthird;
+    int64_t nA;
+    int64_t nB;
+    int64_t chunk_len;
+    int32_t chunks;
+};
+struct X3Batch {
+    int32_t n;
+    X3Job j[kPairs];
+};
+
+__global__ __launch_bounds__(256, 2) void match_topk_x3_kernel(const X3Batch b)
+{
+    int64_t local;
+    const int k = find_job(b, (int64_t)blockIdx.x,
+                           [](const X3Job& J) { return (J.nA + kX3QB - 1) / kX3QB * J.chunks; },
+                           local);
+    if (k < 0) return;
+    const X3Job& J = b.j[k];
+    const int64_t qblocks = (J.nA + kX3QB - 1) / kX3QB;
+    const int chunk = (int)(local / qblocks);
+    topk_x3_item(J.A, J.nA, J.Bhl, J.nB, J.nrm, J.chunk_len, J.chunks, J.cidx, J.cscore, J.cthird,
+                 local - chunk * qblocks, chunk);
+}
+
+struct RescoreX3Job {
+    const float* A;
+    const float* B;
+    const int32_t* cidx;
+    const float* cscore;
+    const float* cthird;
+    const uint32_t* maxbits;
+    int32_t* match;
+    float* d1;
+    float* d2;
+    uint32_t* fb_count;
+    int32_t* fb_list;
+    int64_t nA;
+    int32_t chunks;
+};
+struct RescoreX3Batch {
+    int32_t n;
+    double ratio;
+    float abs_thresh;
+    RescoreX3Job j[kPairs];
+};
+
+__global__ __launch_bounds__(256) void rescore_x3_kernel(const RescoreX3Batch b)
+{
+    int64_t local;
+    const int k = find_job(b, (int64_t)blockIdx.x,
+                           [](const RescoreX3Job& J) { return (J.nA + 3) / 4; }, local);
+    if (k < 0) return;
+    const RescoreX3Job& J = b.j[k];
+    const int64_t q = local * 4 + (threadIdx.x >> 6);
+    if (q < J.nA)
+        rescore_x3_query(J.A, J.B, J.chunks, q, J.cidx, J.cscore, J.cthird, J.maxbits, b.ratio,
+                         b.abs_thresh, J.match, J.d1, J.d2, J.fb_count, J.fb_list);
+}
+
+// Per-pair counters: zeroed before a launch sequence, summed into the
+// caller's statistics word after it.
+struct CounterBatch {
+    int32_t n;
+    uint32_t* c[kPairs];
+};
+
+__global__ void zero_counters_kernel(const CounterBatch b, int words)
+{
+    const int k = threadIdx.x / 4, w = threadIdx.x % 4;
+    if (k < b.n && w < words) b.c[k][w] = 0u;
+}
+
+__global__ void add_counters_kernel(const CounterBatch b, uint32_t* dst)
+{
+    if (threadIdx.x == 0) {
+        uint32_t s = *dst;
+        for (int k = 0; k < b.n; ++k) s += *b.c[k];
+        *dst = s;
+    }
 }
 
 // ------------------------------------------------------------------ layout --
@@ -1023,91 +1250,15 @@ size_t match_workspace_bytes(int64_t nA, int64_t nB, const lpsift_match_params* 
 
 namespace {
 
-int launch_f32(const float* A, int64_t nA, const float* B, int64_t nB, const MatchPlan& pf,
-               const lpsift_match_params* mp, char* base, int32_t* match, float* d1, float* d2,
-               hipStream_t stream)
+// Quantised approximate paths (precision 1, 2), one pair with nA, nB > 0.
+int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStream_t stream)
 {
-    const WsF32 L = ws_f32(nA, nB, pf);
-    float* nrm = reinterpret_cast<float*>(base + L.nrm);
-    int32_t* cidx = reinterpret_cast<int32_t*>(base + L.cidx);
-    float* cscore = reinterpret_cast<float*>(base + L.cscore);
-    if (nB > 0) {
-        hipLaunchKernelGGL(sqnorm_kernel, dim3((unsigned)((nB + 15) / 16)), dim3(256), 0, stream,
-                           B, nB, nrm, (uint32_t*)nullptr);
-        const dim3 grid((unsigned)((nA + kQB - 1) / kQB), (unsigned)pf.chunks);
-        hipLaunchKernelGGL(match_topk_f32_kernel, grid, dim3(256), 0, stream, A, nA, B, nB, nrm,
-                           pf.chunk_len, pf.chunks, (const int32_t*)nullptr,
-                           (const uint32_t*)nullptr, cidx, cscore);
-    }
-    hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)((nA + 3) / 4)), dim3(256), 0, stream, A,
-                       nA, B, (nB > 0) ? pf.chunks : 0, (const int32_t*)nullptr,
-                       (const uint32_t*)nullptr, cidx, cscore, mp->ratio, mp->abs_thresh, match,
-                       d1, d2);
-    return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
-}
-
-}  // namespace
-
-int launch_match(const float* A, int64_t nA, const float* B, int64_t nB,
-                 const lpsift_match_params* mp, void* ws, int32_t* match, float* d1, float* d2,
-                 hipStream_t stream)
-{
-    if (nA == 0) return LPSIFT_OK;
-    char* base = static_cast<char*>(ws);
-
-    if (mp->precision == 0 || nB == 0) {
-        const MatchPlan pf = plan_fp32(nA, nB, mp->precision == 0 ? mp->b_chunks : 0);
-        const int st = launch_f32(A, nA, B, nB, pf, mp, base, match, d1, d2, stream);
-        if (st != LPSIFT_OK) return st;
-        // counters are not used here: report zero re-matched queries
-        if (mp->stats) {
-            hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream,
-                               static_cast<uint32_t*>(mp->stats), 1);
-        }
-        return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
-    }
-
+    const int64_t nA = io.nA, nB = io.nB;
+    const float* A = io.A;
+    const float* B = io.B;
+    char* base = static_cast<char*>(io.ws);
     const MatchPlan p = plan_match(nA, nB, mp);
     const dim3 gr((unsigned)((nA + 3) / 4));
-
-    if (mp->precision == 3) {
-        const MatchPlan pf = plan_fallback(nA, nB);
-        const WsX3 L = ws_x3(nA, nB, p, pf);
-        const WsF32 F = ws_f32(nA, nB, pf);
-        uint32_t* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);   // [0] fallbacks, [1..3] maxima
-        int32_t* cidx = reinterpret_cast<int32_t*>(base + L.cidx);
-        float* cscore = reinterpret_cast<float*>(base + L.cscore);
-        float* cthird = reinterpret_cast<float*>(base + L.cthird);
-        int32_t* fb = reinterpret_cast<int32_t*>(base + L.fb);
-        char* fbase = base + L.f32;
-        float* nrm = reinterpret_cast<float*>(fbase + F.nrm);
-        int32_t* fidx = reinterpret_cast<int32_t*>(fbase + F.cidx);
-        float* fscore = reinterpret_cast<float*>(fbase + F.cscore);
-
-        uint8_t* bhl = reinterpret_cast<uint8_t*>(base + L.bhl);
-        hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, 4);
-        hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((nB + 15) / 16)), dim3(256), 0,
-                           stream, B, nB, nrm, bhl, cnt + 1);
-        const dim3 grid((unsigned)((nA + kX3QB - 1) / kX3QB), (unsigned)p.chunks);
-        hipLaunchKernelGGL(match_topk_x3_kernel, grid, dim3(256), 0, stream, A, nA, bhl, nB, nrm,
-                           p.chunk_len, p.chunks, cidx, cscore, cthird);
-        hipLaunchKernelGGL(rescore_x3_kernel, gr, dim3(256), 0, stream, A, nA, B, p.chunks, cidx,
-                           cscore, cthird, (const uint32_t*)(cnt + 1), mp->ratio, mp->abs_thresh,
-                           match, d1, d2, cnt, fb);
-        // queries the bound could not certify: FP32 path over the device-side list
-        const dim3 gf((unsigned)((nA + kQB - 1) / kQB), (unsigned)pf.chunks);
-        hipLaunchKernelGGL(match_topk_f32_kernel, gf, dim3(256), 0, stream, A, nA, B, nB, nrm,
-                           pf.chunk_len, pf.chunks, fb, cnt, fidx, fscore);
-        hipLaunchKernelGGL(rescore_kernel, gr, dim3(256), 0, stream, A, nA, B, pf.chunks, fb, cnt,
-                           fidx, fscore, mp->ratio, mp->abs_thresh, match, d1, d2);
-        if (mp->stats) {
-            hipLaunchKernelGGL(copy_u32_kernel, dim3(1), dim3(1), 0, stream,
-                               static_cast<uint32_t*>(mp->stats), cnt);
-        }
-        return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
-    }
-
-    // quantised approximate paths
     const WsLp L = ws_lp(nA, nB, mp->precision, p);
     float* scal = reinterpret_cast<float*>(base + L.scal);
     uint32_t* counters = reinterpret_cast<uint32_t*>(scal);   // [1], [2] max bits
@@ -1133,8 +1284,8 @@ int launch_match(const float* A, int64_t nA, const float* B, int64_t nB,
         hipLaunchKernelGGL((match_topk_lp_kernel<1, kLpKeepBf16>), grid, dim3(256), 0, stream, aq,
                            sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
         hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepBf16>), gr, dim3(256), 0, stream, A, nA, B,
-                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, match,
-                           d1, d2);
+                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, io.match,
+                           io.d1, io.d2);
     } else {
         hipLaunchKernelGGL(quantize_kernel<2>, gq, dim3(256), 0, stream, A, nA, aq, sa,
                            (uint32_t*)nullptr);
@@ -1144,14 +1295,172 @@ int launch_match(const float* A, int64_t nA, const float* B, int64_t nB,
         hipLaunchKernelGGL((match_topk_lp_kernel<2, kLpKeepFp8>), grid, dim3(256), 0, stream, aq,
                            sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
         hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepFp8>), gr, dim3(256), 0, stream, A, nA, B,
-                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, match,
-                           d1, d2);
-    }
-    if (mp->stats) {
-        hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream,
-                           static_cast<uint32_t*>(mp->stats), 1);
+                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, io.match,
+                           io.d1, io.d2);
     }
     return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
+}
+
+// Grid of a launch whose item count is only known on the device: at most
+// `cap` workgroups stride over at most `most` items.
+unsigned strided_grid(int64_t most, int64_t cap)
+{
+    return (unsigned)((most < cap) ? (most > 0 ? most : 1) : cap);
+}
+
+// Per-pair workspace pointers of the FP32 and split paths. The norms (and
+// split rows) of a candidate set shared by several pairs of the call live in
+// the workspace of the first pair that uses it (its owner).
+struct PairPtrs {
+    MatchPlan p, pf;
+    float* nrm;
+    uint8_t* bhl;
+    uint32_t* cnt;         // split: [0] re-matched queries, [1..3] row maxima of B
+    int32_t* cidx;
+    float* cscore;
+    float* cthird;
+    int32_t* fb;
+    int32_t* fidx;
+    float* fscore;
+};
+
+PairPtrs pair_ptrs(const MatchPairIO& io, const lpsift_match_params* mp)
+{
+    PairPtrs r{};
+    char* base = static_cast<char*>(io.ws);
+    if (mp->precision == 3) {
+        r.p = plan_match(io.nA, io.nB, mp);
+        r.pf = plan_fallback(io.nA, io.nB);
+        const WsX3 L = ws_x3(io.nA, io.nB, r.p, r.pf);
+        const WsF32 F = ws_f32(io.nA, io.nB, r.pf);
+        char* fbase = base + L.f32;
+        r.cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+        r.bhl = reinterpret_cast<uint8_t*>(base + L.bhl);
+        r.cidx = reinterpret_cast<int32_t*>(base + L.cidx);
+        r.cscore = reinterpret_cast<float*>(base + L.cscore);
+        r.cthird = reinterpret_cast<float*>(base + L.cthird);
+        r.fb = reinterpret_cast<int32_t*>(base + L.fb);
+        r.nrm = reinterpret_cast<float*>(fbase + F.nrm);
+        r.fidx = reinterpret_cast<int32_t*>(fbase + F.cidx);
+        r.fscore = reinterpret_cast<float*>(fbase + F.cscore);
+    } else {
+        r.pf = plan_fp32(io.nA, io.nB, mp->precision == 0 ? mp->b_chunks : 0);
+        const WsF32 F = ws_f32(io.nA, io.nB, r.pf);
+        r.nrm = reinterpret_cast<float*>(base + F.nrm);
+        r.fidx = reinterpret_cast<int32_t*>(base + F.cidx);
+        r.fscore = reinterpret_cast<float*>(base + F.cscore);
+    }
+    return r;
+}
+
+}  // namespace
+
+int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* mp,
+                       hipStream_t stream)
+{
+    uint32_t* stats = static_cast<uint32_t*>(mp->stats);
+    if (stats) hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream, stats, 1);
+
+    // pairs with queries; of those, the ones with candidates
+    std::vector<int> act;
+    for (int i = 0; i < n; ++i)
+        if (io[i].nA > 0) act.push_back(i);
+    std::vector<PairPtrs> pp(n);
+    std::vector<int> owner(n, -1);
+    for (int i : act) {
+        pp[i] = pair_ptrs(io[i], mp);
+        if (io[i].nB == 0) continue;
+        owner[i] = i;
+        for (int k : act) {
+            if (k >= i) break;
+            if (io[k].nB == io[i].nB && io[k].B == io[i].B) {
+                owner[i] = owner[k];
+                break;
+            }
+        }
+    }
+    const bool lp = (mp->precision == 1 || mp->precision == 2);
+
+    for (size_t b0 = 0; b0 < act.size(); b0 += kPairs) {
+        const size_t b1 = (b0 + kPairs < act.size()) ? b0 + kPairs : act.size();
+        RowsBatch rows{};
+        F32Batch main{}, fall{};
+        X3Batch x3{};
+        RescoreX3Batch rx3{};
+        RescoreF32Batch rf{};
+        CounterBatch cnt{};
+        rx3.ratio = rf.ratio = mp->ratio;
+        rx3.abs_thresh = rf.abs_thresh = mp->abs_thresh;
+        int64_t rows_wg = 0, main_wg = 0, x3_wg = 0, rx3_wg = 0, fall_most = 0, rf_most = 0;
+        for (size_t a = b0; a < b1; ++a) {
+            const int i = act[a];
+            const MatchPairIO& P = io[i];
+            const PairPtrs& Q = pp[i];
+            if (P.nB == 0) {            // no candidates: every query rejected
+                rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, nullptr, nullptr,
+                                             P.match, P.d1, P.d2, P.nA, 0};
+                rf_most += (P.nA + 3) / 4;
+                continue;
+            }
+            if (lp) {
+                const int st = launch_lp_pair(P, mp, stream);
+                if (st != LPSIFT_OK) return st;
+                continue;
+            }
+            const PairPtrs& O = pp[owner[i]];
+            if (owner[i] == i) {
+                rows.j[rows.n++] = RowsJob{P.B, Q.nrm, mp->precision == 3 ? Q.bhl : nullptr,
+                                           Q.cnt ? Q.cnt + 1 : nullptr, P.nB};
+                rows_wg += (P.nB + 15) / 16;
+            }
+            if (mp->precision == 0) {
+                main.j[main.n++] = F32Job{P.A, nullptr, nullptr, P.B, O.nrm, Q.fidx, Q.fscore,
+                                          P.nA, P.nB, Q.pf.chunk_len, Q.pf.chunks};
+                main_wg += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
+                rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, Q.fidx, Q.fscore,
+                                             P.match, P.d1, P.d2, P.nA, Q.pf.chunks};
+                rf_most += (P.nA + 3) / 4;
+                continue;
+            }
+            // split path, then the FP32 re-match of the queries it did not certify
+            cnt.c[cnt.n++] = Q.cnt;
+            x3.j[x3.n++] = X3Job{P.A, O.bhl, O.nrm, Q.cidx, Q.cscore, Q.cthird, P.nA, P.nB,
+                                 Q.p.chunk_len, Q.p.chunks};
+            x3_wg += (P.nA + kX3QB - 1) / kX3QB * Q.p.chunks;
+            rx3.j[rx3.n++] = RescoreX3Job{P.A, P.B, Q.cidx, Q.cscore, Q.cthird, O.cnt + 1,
+                                          P.match, P.d1, P.d2, Q.cnt, Q.fb, P.nA, Q.p.chunks};
+            rx3_wg += (P.nA + 3) / 4;
+            fall.j[fall.n++] = F32Job{P.A, Q.fb, Q.cnt, P.B, O.nrm, Q.fidx, Q.fscore, P.nA, P.nB,
+                                      Q.pf.chunk_len, Q.pf.chunks};
+            fall_most += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
+            rf.j[rf.n++] = RescoreF32Job{P.A, P.B, Q.fb, Q.cnt, Q.fidx, Q.fscore, P.match, P.d1,
+                                         P.d2, P.nA, Q.pf.chunks};
+            rf_most += (P.nA + 3) / 4;
+        }
+        // the split rows' maxima are accumulated with atomics: zero them first
+        if (cnt.n > 0)
+            hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, 4);
+        if (rows.n > 0)
+            hipLaunchKernelGGL(rows_kernel, dim3((unsigned)rows_wg), dim3(256), 0, stream, rows);
+        if (main.n > 0)
+            hipLaunchKernelGGL(match_topk_f32_kernel, dim3((unsigned)main_wg), dim3(256), 0,
+                               stream, main);
+        if (x3.n > 0) {
+            hipLaunchKernelGGL(match_topk_x3_kernel, dim3((unsigned)x3_wg), dim3(256), 0, stream,
+                               x3);
+            hipLaunchKernelGGL(rescore_x3_kernel, dim3((unsigned)rx3_wg), dim3(256), 0, stream,
+                               rx3);
+            hipLaunchKernelGGL(match_topk_f32_kernel, dim3(strided_grid(fall_most, 1024)),
+                               dim3(256), 0, stream, fall);
+        }
+        if (rf.n > 0)
+            hipLaunchKernelGGL(rescore_f32_kernel, dim3(strided_grid(rf_most, 8192)), dim3(256), 0,
+                               stream, rf);
+        if (stats && cnt.n > 0)
+            hipLaunchKernelGGL(add_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, stats);
+        if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+    }
+    return LPSIFT_OK;
 }
 
 }  // namespace lpsift

@@ -1,0 +1,78 @@
+"""Many pairs in one lpsift_match call.
+
+The FP32 and split paths run up to 16 pairs per launch and compute the norms
+of a registered set shared by several pairs once; every pair's lists must be
+bit-identical to the same pair matched alone (the per-pair arithmetic does not
+depend on the batch), and the split path's re-match count must be the sum of
+the per-pair counts. One pair per call is itself checked against the oracle in
+test_gpu_match.py; here one pair of the batch is checked again (rule (i)).
+"""
+import numpy as np
+import pytest
+
+import synth
+import paper_2405_08578_amd as lp
+from gpu_util import say
+from test_gpu_match import check_rule_i
+
+pytestmark = pytest.mark.gpu
+
+
+def descriptor_sets(sizes, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = synth.random_unit_rows(max(sizes) + 1, 128, rng)
+    out = []
+    for n in sizes:
+        src = rng.integers(0, len(base), n)
+        out.append(synth.noisy_copies(base, src, 0.08, rng).astype(np.float32).reshape(n, 128))
+    return out
+
+
+def all_pairs(n):
+    return [(i, j) for i in range(n) for j in range(n) if i != j]
+
+
+def host(r):
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+@pytest.mark.parametrize("prec", [0, 3, 1, 2])
+def test_batch_equals_pairs_alone(gpu, prec):
+    import torch
+    sizes = [700, 450, 1000, 37, 0, 260]            # 30 ordered pairs: two batches of 16 and 14
+    sets = [torch.from_numpy(s).to(gpu) for s in descriptor_sets(sizes, 40 + prec)]
+    pairs = all_pairs(len(sets))
+    say("batched match", prec, len(pairs), "pairs")
+    st_all = torch.zeros(1, dtype=torch.int32, device=gpu)
+    res = lp.match([sets[i] for i, _ in pairs], [sets[j] for _, j in pairs], precision=prec,
+                   stats=st_all)
+    total = 0
+    for (i, j), r in zip(pairs, res):
+        st = torch.zeros(1, dtype=torch.int32, device=gpu)
+        alone = lp.match([sets[i]], [sets[j]], precision=prec, stats=st)[0]
+        a, b = host(r), host(alone)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (i, j, k)
+        total += st.item()
+        if sizes[j] == 0:
+            assert np.all(a["match"] == -1) and np.all(np.isinf(a["d1"]))
+    assert st_all.item() == total
+    if prec == 0:
+        i, j = pairs[1]
+        check_rule_i(sets[i].cpu().numpy(), sets[j].cpu().numpy(), host(res[1]))
+
+
+@pytest.mark.parametrize("chunks", [1, 5, 16])
+def test_batch_shared_sets_chunks(gpu, chunks):
+    import torch
+    sets = [torch.from_numpy(s).to(gpu) for s in descriptor_sets([900, 1300, 513], 77)]
+    # the same registered set in several pairs, and a repeated pair
+    pairs = [(0, 1), (2, 1), (1, 0), (2, 0), (0, 1), (1, 2)]
+    say("batched match, shared sets, chunks", chunks)
+    res = lp.match([sets[i] for i, _ in pairs], [sets[j] for _, j in pairs], b_chunks=chunks)
+    for (i, j), r in zip(pairs, res):
+        alone = lp.match([sets[i]], [sets[j]], b_chunks=chunks)[0]
+        a, b = host(r), host(alone)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (i, j, k)
+    check_rule_i(sets[2].cpu().numpy(), sets[1].cpu().numpy(), host(res[1]))
