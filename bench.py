@@ -7,11 +7,14 @@ registered set with the 0.8 ratio test: the whole GPU hot path for one pair,
 inputs resident in HBM before the timed region.
 
 Prints ONE JSON line: value = pairs/s; detect+describe Mpix/s as a side field;
-a roofline object for the dominant kernel (the FP32 matrix-core contraction of
-the matcher) from HIP events recorded around every matcher call on the stream
-the kernels run on; and the FP64 oracle timed on a bounded sample on the host.
+per-kernel device times from the library's timing facility (HIP events
+recorded around every launch on the stream it runs on) and from them a roofline
+object for the dominant kernel (the FP32 matrix-core contraction of the
+matcher); side fields for the reduced-precision matchers and for the 9-tile
+all-pairs workload (tuned work split, HIP-graph replay); and the FP64 oracle
+timed on a bounded sample on the host.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-tiles]
 """
 import argparse
 import json
@@ -33,6 +36,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tiles", action="store_true",
+                    help="skip the 9-tile all-pairs side measurement")
     ap.add_argument("--cpu-queries", type=int, default=12288,
                     help="reference descriptors in the oracle's timed match sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -88,6 +93,113 @@ def cpu_baseline(pair, Ls, nq_sample):
             "seconds_per_pair": t_pair}
 
 
+def kernel_table(t, steps):
+    """Mean device ms per step and per launch of each timed kernel."""
+    return {k: {"ms_per_step": round(v["ms"] / steps, 4),
+                "launches_per_step": v["launches"] / steps,
+                "ms_per_launch": round(v["ms"] / max(v["launches"], 1), 4)}
+            for k, v in t.items() if v["launches"] > 0}
+
+
+def timed(fn, steps, stream):
+    """Wall-clock and event ms per call of fn over `steps` calls."""
+    import torch
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e[0].record(stream)
+    for _ in range(steps):
+        fn()
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return 1000.0 * wall / steps, e[0].elapsed_time(e[1]) / steps
+
+
+def bench_tiles(args, dev):
+    """All-pairs matching of the 9 shuffled tiles: detect + describe all tiles
+    and match all 36 pairs (i < j) per step, the work split tuned on the
+    device, the step captured in a HIP graph and replayed."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2405_08578_amd as lp
+    from paper_2405_08578_amd.allpairs import AllPairs
+
+    tiles = synth.make_tiles()
+    Ls = [16, 32, 64, 128]
+    P = lp.Params(Ls)
+    imgs = [torch.from_numpy(t).to(dev) for t in tiles.images]
+    stream = torch.cuda.current_stream()
+    steps = max(2, args.steps // 2)
+    res = {"workload": "9 shuffled uint8 tiles 2600-2800 x 1600-1800 cut from a 7000x4500 "
+                       "synthetic world (3x3 grid, 25-35 % overlaps, per-tile similarity and "
+                       "gain): detect+orient+describe all tiles, FP32 match of all 36 pairs "
+                       "(i < j) with ratio 0.8",
+           "tile_shapes": [list(t.shape) for t in tiles.images], "pairs": 36, "L": Ls}
+
+    # tune the candidate-range split on the real descriptor sets
+    ap = AllPairs(imgs, P, precision=0)
+    ap.run()
+    torch.cuda.synchronize()
+    A = [ap.desc[i] for i, _ in ap.pairs]
+    B = [ap.desc[j] for _, j in ap.pairs]
+    tunes = {}
+    for prec in (0, 3):
+        tunes[prec] = lp.match_tune(A, B, precision=prec, candidates=(1, 2, 3, 4, 6, 8), reps=1)
+    res["tuned_b_chunks"] = {"fp32": tunes[0]["b_chunks"], "split": tunes[3]["b_chunks"]}
+    res["tune_ms"] = {"fp32": [round(v, 2) for v in tunes[0]["ms"]],
+                      "split": [round(v, 2) for v in tunes[3]["ms"]],
+                      "candidates": tunes[0]["candidates"]}
+    del A, B, ap
+    torch.cuda.empty_cache()
+
+    n_kp = [lp.num_keypoints(t.shape[0], t.shape[1], P) for t in imgs]
+    flops = sum(2.0 * n_kp[i] * n_kp[j] * 128 for i, j in
+                [(i, j) for i in range(9) for j in range(i + 1, 9)])
+    ref_lists = None
+    variants = {}
+    for prec, name in ((0, "fp32"), (3, "split_bf16x3_certified"), (1, "bf16"), (2, "fp8")):
+        bc = tunes[prec]["b_chunks"] if prec in tunes else 0
+        ap = AllPairs(imgs, P, precision=prec, b_chunks=bc)
+        for _ in range(max(1, args.warmup)):
+            ap.run()
+        eager_wall, eager_ev = timed(ap.run, steps, stream)
+        # per-kernel device time of one eager step
+        lp.timing_enable(True)
+        ap.run()
+        kt = kernel_table(lp.timing_read(), 1)
+        lp.timing_enable(False)
+        ap.capture()
+        for _ in range(max(1, args.warmup)):
+            ap.replay()
+        wall, ev = timed(ap.replay, steps, stream)
+        lists = [o["match"].cpu().numpy() for o in ap.out]
+        v = {"ms_per_step_graph": round(wall, 3), "ms_per_step_eager": round(eager_wall, 3),
+             "pairs_per_s": round(36 * 1000.0 / wall, 3),
+             "detect_describe_match_mpix_per_s": round(ap.megapixels * 1000.0 / wall, 1),
+             "kernels": kt}
+        key = {0: "match_fp32", 3: "match_split"}.get(prec, "match_lowp")
+        if key in kt:
+            v["contraction_tflops" + ("" if prec == 0 else "_equiv")] = round(
+                flops / (kt[key]["ms_per_step"] * 1e-3) / 1e12, 1)
+        if prec == 3:
+            v["queries_rematched_fp32"] = int(ap.stats.item())
+        if ref_lists is None:
+            ref_lists = lists
+            v["matches"] = int(sum((m >= 0).sum() for m in lists))
+        else:
+            same = sum(int((a == b).sum()) for a, b in zip(lists, ref_lists))
+            v["list_agreement_with_fp32"] = round(same / sum(len(m) for m in lists), 6)
+        variants[name] = v
+        del ap
+        torch.cuda.empty_cache()
+    res["descriptors"] = int(sum(n_kp))
+    res["match_gflop_per_step"] = round(flops / 1e9, 1)
+    res["variants"] = variants
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -122,16 +234,10 @@ def main():
              "d2": torch.empty(n_kp, dtype=torch.float32, device=dev)}]
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
+    def step():
         lp.detect(imgs, P, out=kps, stream=stream)
         lp.describe(imgs, kps, P, workspace=ws_d, theta=theta, desc=desc, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
         lp.match([desc[0]], [desc[1]], workspace=ws_m, out=mout, stream=stream)
-        if ev is not None:
-            ev[2].record(stream)
 
     if args.copy_probe_mb > 0:
         nb = args.copy_probe_mb << 20
@@ -145,24 +251,36 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # timed region: every launch of the path's kernels is bracketed by HIP
+    # events on its own stream (the library's timing facility)
+    lp.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
+    for _ in range(args.steps):
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kt_raw = lp.timing_read()
+    lp.timing_enable(False)
+    kt = kernel_table(kt_raw, args.steps)
 
-    dd_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    m_ms = [e[1].elapsed_time(e[2]) for e in evs]
     ms_per_step = 1000.0 * wall / args.steps
     pairs_per_s = 1000.0 / ms_per_step
     mpix = 2 * h * w / 1e6
-    dd_avg = sum(dd_ms) / len(dd_ms)
-    m_avg = sum(m_ms) / len(m_ms)
+    dd_ms = sum(kt[k]["ms_per_step"] for k in ("detect", "gradient", "describe") if k in kt)
+    m_ms = sum(kt[k]["ms_per_step"] for k in kt if k.startswith("match"))
     flops = 2.0 * n_kp * n_kp * 128
-    achieved = flops / (m_avg * 1e-3) / 1e12
+    k_ms = kt["match_fp32"]["ms_per_launch"]
+    achieved = flops / (k_ms * 1e-3) / 1e12
     n_match = int((mout[0]["match"] >= 0).sum().item())
+    # algorithmic bytes (see the kernel notes): detect reads every pixel and
+    # writes 15 B per keypoint slot; the gradient pass reads 1 B and writes 8 B
+    # per pixel
+    det_bytes = 2 * (h * w + n_kp * 15)
+    grad_bytes = 2 * h * w * 9
+    rates = {"detect_GBps": round(det_bytes / (kt["detect"]["ms_per_step"] * 1e-3) / 1e9, 1),
+             "gradient_GBps": round(grad_bytes / (kt["gradient"]["ms_per_step"] * 1e-3) / 1e9, 1),
+             "describe_keypoints_per_s": round(2 * n_kp / (kt["describe"]["ms_per_step"] * 1e-3), 0)}
 
     out = {
         "metric": METRIC,
@@ -181,15 +299,17 @@ def main():
                                f"random similarity, IoU {pair.iou:.2f}): detect+orient+describe "
                                f"both images, FP32 brute-force match with ratio 0.8",
                    "L": Ls, "descriptors_per_image": n_kp, "desc_dim": 128},
-        "detect_describe_mpix_per_s": round(mpix / (dd_avg * 1e-3), 1),
-        "detect_describe_ms": round(dd_avg, 4),
-        "match_ms": round(m_avg, 4),
+        "detect_describe_mpix_per_s": round(mpix / (dd_ms * 1e-3), 1),
+        "detect_describe_ms": round(dd_ms, 4),
+        "match_ms": round(m_ms, 4),
         "matches": n_match,
+        "kernels": kt,
+        "kernel_rates": rates,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4),
                      "traffic": measured_traffic(),
-                     "kernel": "matcher call (norms + FP32 MFMA contraction/top-k + rescore), "
-                               f"{flops / 1e9:.1f} GFLOP per call"},
+                     "kernel": f"match_topk_f32_kernel, {flops / 1e9:.1f} GFLOP per launch, "
+                               f"{k_ms:.4f} ms per launch (HIP events on its stream)"},
     }
     # reduced-precision contractions on the same descriptors (side fields): the
     # split BF16x3 path is certified against the FP32 path, BF16 and FP8 are
@@ -205,23 +325,21 @@ def main():
                                 stream=stream, stats=stats)
         for _ in range(max(1, args.warmup)):
             call()
-        torch.cuda.synchronize()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record(stream)
-        for _ in range(args.steps):
-            call()
-        e[1].record(stream)
-        torch.cuda.synchronize()
-        ms = e[0].elapsed_time(e[1]) / args.steps
+        _, ms = timed(call, args.steps, stream)
         same = (outl[0]["match"] == ref).float().mean().item()
         lowp[name] = {"match_ms": round(ms, 4),
-                      "pairs_per_s": round(1000.0 / (dd_avg + ms), 2),
+                      "pairs_per_s": round(1000.0 / (dd_ms + ms), 2),
                       "contraction_tflops_equiv": round(flops / (ms * 1e-3) / 1e12, 1),
                       "list_agreement_with_fp32": round(same, 6)}
         if prec == 3:
             lowp[name]["queries_rematched_fp32"] = int(stats.item())
         del wsl, outl
     out["low_precision_match"] = lowp
+    del kps, theta, desc, ws_d, ws_m, mout
+    torch.cuda.empty_cache()
+
+    if not args.no_tiles:
+        out["all_pairs_tiles"] = bench_tiles(args, dev)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(pair, Ls, args.cpu_queries)

@@ -42,6 +42,20 @@ enum {
 #define LPSIFT_MAX_SCALES 8
 #define LPSIFT_DESC_DIM 128   /* d x d x 8 with d = 4 */
 
+/* Kernels booked by the optional timing facility (lpsift_timing_*). */
+enum lpsift_kernel {
+    LPSIFT_KERNEL_DETECT = 0,          /* window extrema of every scale (Eq. 2) */
+    LPSIFT_KERNEL_GRADIENT = 1,        /* gradient magnitude and angle field (Eq. 5) */
+    LPSIFT_KERNEL_DESCRIBE = 2,        /* orientation + descriptor per keypoint */
+    LPSIFT_KERNEL_MATCH_NORMS = 3,     /* |b|^2 (and split rows) of the registered sets */
+    LPSIFT_KERNEL_MATCH_FP32 = 4,      /* FP32 matrix-core contraction with top-k */
+    LPSIFT_KERNEL_MATCH_SPLIT = 5,     /* split-BF16 contraction with top-k */
+    LPSIFT_KERNEL_MATCH_RESCORE = 6,   /* FP32 rescore + ratio test (all precisions) */
+    LPSIFT_KERNEL_MATCH_REMATCH = 7,   /* FP32 re-match of uncertified split queries */
+    LPSIFT_KERNEL_MATCH_LOWP = 8,      /* BF16 / FP8 contraction with top-k */
+    LPSIFT_KERNEL_COUNT = 9
+};
+
 /* Method parameters (Sec. 2.2-2.3).
  *  n_scales  number of window sizes, 1..LPSIFT_MAX_SCALES
  *  L         window sides, strictly ascending, L[0] >= 4. On the GPU each L must
@@ -192,6 +206,35 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
                  const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
                  void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                  float* const* d2, void* stream);
+
+/* Autotuner of the candidate-range split of lpsift_match (its b_chunks): for
+ * each of n_candidates values (each 1..16) it runs the call once untimed and
+ * reps times timed on `stream`, stores the mean milliseconds per call in
+ * ms[c] (host array of n_candidates) and the fastest value in *best (host).
+ * All other arguments are those of lpsift_match; the workspace must satisfy
+ * every candidate (lpsift_match_workspace_size with b_chunks set to it). The
+ * outputs hold the last run's lists. Synchronises the stream, so it cannot be
+ * captured in a graph. Errors: EINVAL (bad candidate, n_candidates < 1, reps
+ * outside 1..1000, null ms/best, or any lpsift_match argument error),
+ * ECAPACITY, EHIP. */
+int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float* const* descB,
+                      const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
+                      const int32_t* candidates, int32_t n_candidates, int32_t reps,
+                      void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
+                      float* const* d2, float* ms, int32_t* best, void* stream);
+
+/* Kernel timing, a profiling aid. lpsift_timing_enable(1) resets the sums
+ * and makes every later launch of the kernels listed in lpsift_kernel bracket
+ * itself with two HIP events recorded on its stream (a few microseconds per
+ * launch); lpsift_timing_enable(0) resets and stops. lpsift_timing_read waits
+ * for every recorded event and returns, for one kernel, the summed device
+ * milliseconds and the number of timed launches since the reset. Host-side
+ * state shared by all streams and devices of the process; keep it disabled
+ * while capturing a graph. Errors: EINVAL (bad kernel id or null pointer),
+ * EHIP (an event could not be created, recorded or read; the sums then miss
+ * those launches). */
+int lpsift_timing_enable(int32_t on);
+int lpsift_timing_read(int32_t kernel, double* ms, int64_t* launches);
 
 /* Homography between matched pairs by RANSAC (Sec. 2.5, Eq. 7), on the host in
  * FP64; no GPU involvement and no stream. Eq. 8's rigid transform is the special

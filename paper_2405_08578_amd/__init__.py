@@ -53,7 +53,8 @@ class lpsift_match_params(ctypes.Structure):
 
 EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
            "lpsift_describe_workspace_size", "lpsift_describe", "lpsift_match_workspace_size",
-           "lpsift_match", "lpsift_ransac_host")
+           "lpsift_match", "lpsift_match_tune", "lpsift_timing_enable", "lpsift_timing_read",
+           "lpsift_ransac_host")
 
 _lib = None
 
@@ -93,6 +94,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_match.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
                                  P(lpsift_match_params), c_vp, ctypes.c_size_t, P(c_vp), P(c_vp),
                                  P(c_vp), c_vp]
+    lib.lpsift_match_tune.restype = ctypes.c_int
+    lib.lpsift_match_tune.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
+                                      P(lpsift_match_params), P(c_i32), c_i32, c_i32, c_vp,
+                                      ctypes.c_size_t, P(c_vp), P(c_vp), P(c_vp), P(c_f32),
+                                      P(c_i32), c_vp]
+    lib.lpsift_timing_enable.restype = ctypes.c_int
+    lib.lpsift_timing_enable.argtypes = [c_i32]
+    lib.lpsift_timing_read.restype = ctypes.c_int
+    lib.lpsift_timing_read.argtypes = [c_i32, P(c_f64), P(c_i64)]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -247,14 +257,8 @@ def match_workspace_size(nA: Sequence[int], nB: Sequence[int], mp: lpsift_match_
                                                   ctypes.byref(mp)))
 
 
-def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
-          b_chunks: int = 0, workspace=None, out=None, stream=None,
-          stats=None) -> List[Dict[str, "object"]]:
-    """Nearest neighbour of every row of descA[p] among descB[p] with the ratio
-    test, for every pair p. stats: optional int32 CUDA tensor [1] that receives
-    the number of queries the BF16 path re-matched in FP32."""
+def _match_args(descA, descB, out, workspace, need):
     import torch
-    lib = load()
     n = len(descA)
     if len(descB) != n or n < 1:
         raise ValueError("descA and descB must be equal-length non-empty lists")
@@ -263,21 +267,115 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
                 or not t.is_contiguous():
             raise ValueError("descriptors must be contiguous float32 CUDA tensors [n, 128]")
     dev = descA[0].device
-    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
     nA = [int(t.shape[0]) for t in descA]
     nB = [int(t.shape[0]) for t in descB]
-    need = match_workspace_size(nA, nB, mp)
     if workspace is None:
-        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        workspace = torch.empty(max(need(nA, nB), 256), dtype=torch.uint8, device=dev)
     if out is None:
         out = [{"match": torch.empty(a, dtype=torch.int32, device=dev),
                 "d1": torch.empty(a, dtype=torch.float32, device=dev),
                 "d2": torch.empty(a, dtype=torch.float32, device=dev)} for a in nA]
     ptr = lambda ts: (c_vp * n)(*[t.data_ptr() for t in ts])
-    _check("lpsift_match", lib.lpsift_match(
-        ptr(descA), (c_i64 * n)(*nA), ptr(descB), (c_i64 * n)(*nB), n, ctypes.byref(mp),
-        workspace.data_ptr(), workspace.numel(), ptr([o["match"] for o in out]),
-        ptr([o["d1"] for o in out]), ptr([o["d2"] for o in out]), _stream(stream)))
+    head = (ptr(descA), (c_i64 * n)(*nA), ptr(descB), (c_i64 * n)(*nB), n)
+    tail = (workspace.data_ptr(), workspace.numel(), ptr([o["match"] for o in out]),
+            ptr([o["d1"] for o in out]), ptr([o["d2"] for o in out]))
+    return out, head, tail
+
+
+def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
+          b_chunks: int = 0, workspace=None, out=None, stream=None,
+          stats=None) -> List[Dict[str, "object"]]:
+    """Nearest neighbour of every row of descA[p] among descB[p] with the ratio
+    test, for every pair p. stats: optional int32 CUDA tensor [1] that receives
+    the number of queries the split path re-matched in FP32 (sum over pairs)."""
+    lib = load()
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
+    out, head, tail = _match_args(descA, descB, out, workspace,
+                                  lambda nA, nB: match_workspace_size(nA, nB, mp))
+    _check("lpsift_match", lib.lpsift_match(*head, ctypes.byref(mp), *tail, _stream(stream)))
+    return out
+
+
+TUNE_CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16)
+
+
+def _bucket(n: int) -> int:
+    """Power-of-two bucket of a descriptor count (tuning cache key)."""
+    return 0 if n <= 0 else 1 << (int(n) - 1).bit_length()
+
+
+def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
+               precision: int = 0, candidates: Sequence[int] = TUNE_CANDIDATES, reps: int = 2,
+               cache: Optional[str] = None, stream=None) -> Dict[str, object]:
+    """Pick the fastest candidate-range split (b_chunks) for this set of pairs
+    by timing lpsift_match_tune on the device. cache: optional JSON file; a
+    result is stored under a key of the device name, precision, pair count and
+    power-of-two buckets of the total query and candidate counts, and reused
+    when the key is present. Returns {"b_chunks", "ms", "candidates", "cached"}."""
+    import json
+    import torch
+    key = None
+    if cache is not None:
+        nq = sum(int(t.shape[0]) for t in descA)
+        nc = sum(int(t.shape[0]) for t in descB)
+        key = "|".join(str(v) for v in (torch.cuda.get_device_name(descA[0].device), precision,
+                                        len(descA), _bucket(nq), _bucket(nc)))
+        if os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                r = dict(table[key])
+                r["cached"] = True
+                return r
+    lib = load()
+    mp = match_params(ratio, abs_thresh, precision, 0, None)
+
+    def need(nA, nB):
+        m = match_params(ratio, abs_thresh, precision, 0, None)
+        b = 0
+        for c in candidates:
+            m.b_chunks = int(c)
+            b = max(b, match_workspace_size(nA, nB, m))
+        return b
+    _, head, tail = _match_args(descA, descB, None, None, need)
+    k = len(candidates)
+    ms = (c_f32 * k)()
+    best = c_i32(0)
+    _check("lpsift_match_tune", lib.lpsift_match_tune(
+        *head, ctypes.byref(mp), (c_i32 * k)(*[int(c) for c in candidates]), k, int(reps), *tail,
+        ms, ctypes.byref(best), _stream(stream)))
+    r = {"b_chunks": int(best.value), "ms": [float(v) for v in ms],
+         "candidates": [int(c) for c in candidates], "cached": False}
+    if cache is not None:
+        table = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        table[key] = {k_: v for k_, v in r.items() if k_ != "cached"}
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    return r
+
+
+KERNELS = ("detect", "gradient", "describe", "match_norms", "match_fp32", "match_split",
+           "match_rescore", "match_rematch", "match_lowp")
+
+
+def timing_enable(on: bool = True):
+    """Reset the per-kernel timing sums and switch timing on or off."""
+    _check("lpsift_timing_enable", load().lpsift_timing_enable(1 if on else 0))
+
+
+def timing_read() -> Dict[str, Dict[str, float]]:
+    """{kernel: {"ms": summed device ms, "launches": n}} since the last reset
+    (waits for the recorded events)."""
+    lib = load()
+    out = {}
+    for k, name in enumerate(KERNELS):
+        ms, n = c_f64(0.0), c_i64(0)
+        _check("lpsift_timing_read", lib.lpsift_timing_read(k, ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = {"ms": ms.value, "launches": int(n.value)}
     return out
 
 

@@ -1,0 +1,92 @@
+"""All-pairs feature matching of an image set (the mosaic workload of Sec. 4:
+every image matched against every other before the homographies are solved).
+
+AllPairs preallocates every buffer once for a fixed list of images — keypoint
+slots, orientations, descriptors, both workspaces and the match lists of the
+N (N - 1) / 2 pairs (i < j, image i as queries, image j as registered set) —
+so that one step is three library calls (detect, describe, match) that
+allocate nothing and never synchronise. The step can run eagerly or be
+captured once into a HIP graph (torch.cuda.CUDAGraph) and replayed: the
+launch sequence is fixed by the image shapes, and replays read the images from
+the same device buffers.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Optional, Tuple
+
+from . import (DESC_DIM, Params, describe, describe_workspace_size, detect, empty_keypoints,
+               match, match_params, match_workspace_size, num_keypoints)
+
+
+def pair_list(n: int) -> List[Tuple[int, int]]:
+    return [(i, j) for i in range(n) for j in range(i + 1, n)]
+
+
+class AllPairs:
+    def __init__(self, images, params: Params, precision: int = 0, b_chunks: int = 0,
+                 ratio: float = 0.8, abs_thresh: float = math.inf):
+        import torch
+        if len(images) < 2:
+            raise ValueError("need at least two images")
+        self.images = list(images)
+        self.params = params
+        self.precision = precision
+        self.b_chunks = b_chunks
+        self.ratio = ratio
+        self.abs_thresh = abs_thresh
+        dev = self.images[0].device
+        self.device = dev
+        self.pairs = pair_list(len(self.images))
+        self.n_kp = [num_keypoints(t.shape[0], t.shape[1], params) for t in self.images]
+        self.kps = [empty_keypoints(n, dev) for n in self.n_kp]
+        self.theta = [torch.empty(n, dtype=torch.float32, device=dev) for n in self.n_kp]
+        self.desc = [torch.empty((n, DESC_DIM), dtype=torch.float32, device=dev)
+                     for n in self.n_kp]
+        self.dws = torch.empty(max(describe_workspace_size(self.images, params), 256),
+                               dtype=torch.uint8, device=dev)
+        self.stats = torch.zeros(1, dtype=torch.int32, device=dev)
+        mp = match_params(ratio, abs_thresh, precision, b_chunks, None)
+        need = match_workspace_size([self.n_kp[i] for i, _ in self.pairs],
+                                    [self.n_kp[j] for _, j in self.pairs], mp)
+        self.mws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        self.out = [{"match": torch.empty(self.n_kp[i], dtype=torch.int32, device=dev),
+                     "d1": torch.empty(self.n_kp[i], dtype=torch.float32, device=dev),
+                     "d2": torch.empty(self.n_kp[i], dtype=torch.float32, device=dev)}
+                    for i, _ in self.pairs]
+        self.graph = None
+
+    @property
+    def megapixels(self) -> float:
+        return sum(t.shape[0] * t.shape[1] for t in self.images) / 1e6
+
+    def run(self, stream=None):
+        """Enqueue one step on `stream` (default: the current stream)."""
+        detect(self.images, self.params, out=self.kps, stream=stream)
+        describe(self.images, self.kps, self.params, workspace=self.dws, theta=self.theta,
+                 desc=self.desc, stream=stream)
+        match([self.desc[i] for i, _ in self.pairs], [self.desc[j] for _, j in self.pairs],
+              ratio=self.ratio, abs_thresh=self.abs_thresh, precision=self.precision,
+              b_chunks=self.b_chunks, workspace=self.mws, out=self.out, stream=stream,
+              stats=self.stats)
+
+    def capture(self, warmup: int = 1):
+        """Capture one step into a graph (after `warmup` eager steps on a side
+        stream, as graph capture requires)."""
+        import torch
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()

@@ -184,13 +184,16 @@ size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t
     return b;
 }
 
-int lpsift_match(const float* const* descA, const int64_t* nA, const float* const* descB,
-                 const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
-                 void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
-                 float* const* d2, void* stream)
+}  // extern "C"
+
+// Everything lpsift_match checks except the workspace size.
+static int check_match_call(const float* const* descA, const int64_t* nA,
+                            const float* const* descB, const int64_t* nB, int32_t n_pairs,
+                            const lpsift_match_params* mp, const void* workspace,
+                            int32_t* const* match, float* const* d1, float* const* d2)
 {
     const int sp = check_match_params(mp);
-    if (sp == LPSIFT_EINVAL) return sp;
+    if (sp != LPSIFT_OK) return sp;
     if (!descA || !nA || !descB || !nB || n_pairs < 1 || !match || !d1 || !d2)
         return LPSIFT_EINVAL;
     for (int i = 0; i < n_pairs; ++i) {
@@ -200,8 +203,19 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
         if ((reinterpret_cast<uintptr_t>(descA[i]) | reinterpret_cast<uintptr_t>(descB[i])) & 15u)
             return LPSIFT_EINVAL;
     }
-    if (sp != LPSIFT_OK) return sp;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    return LPSIFT_OK;
+}
+
+extern "C" {
+
+int lpsift_match(const float* const* descA, const int64_t* nA, const float* const* descB,
+                 const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
+                 void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
+                 float* const* d2, void* stream)
+{
+    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, workspace, match, d1, d2);
+    if (sc != LPSIFT_OK) return sc;
     if (ws_bytes < lpsift_match_workspace_size(nA, nB, n_pairs, mp)) return LPSIFT_ECAPACITY;
     std::vector<MatchPairIO> io(n_pairs);
     char* ws = static_cast<char*>(workspace);
@@ -210,6 +224,61 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
         ws += align_up(match_workspace_bytes(nA[i], nB[i], mp), 256);
     }
     return launch_match_pairs(io.data(), n_pairs, mp, static_cast<hipStream_t>(stream));
+}
+
+int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float* const* descB,
+                      const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
+                      const int32_t* candidates, int32_t n_candidates, int32_t reps,
+                      void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
+                      float* const* d2, float* ms, int32_t* best, void* stream)
+{
+    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, workspace, match, d1, d2);
+    if (sc != LPSIFT_OK) return sc;
+    if (!candidates || n_candidates < 1 || reps < 1 || reps > 1000 || !ms || !best)
+        return LPSIFT_EINVAL;
+    lpsift_match_params m = *mp;
+    for (int c = 0; c < n_candidates; ++c) {
+        if (candidates[c] < 1 || candidates[c] > 16) return LPSIFT_EINVAL;
+        m.b_chunks = candidates[c];
+        const size_t need = lpsift_match_workspace_size(nA, nB, n_pairs, &m);
+        if (need == 0) return LPSIFT_EINVAL;
+        if (ws_bytes < need) return LPSIFT_ECAPACITY;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LPSIFT_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return LPSIFT_EHIP;
+    }
+    int st = LPSIFT_OK;
+    float best_ms = 0.0f;
+    for (int c = 0; c < n_candidates && st == LPSIFT_OK; ++c) {
+        m.b_chunks = candidates[c];
+        // one untimed run, then reps timed runs
+        st = lpsift_match(descA, nA, descB, nB, n_pairs, &m, workspace, ws_bytes, match, d1, d2,
+                          stream);
+        if (st != LPSIFT_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = LPSIFT_EHIP; break; }
+        for (int r = 0; r < reps && st == LPSIFT_OK; ++r)
+            st = lpsift_match(descA, nA, descB, nB, n_pairs, &m, workspace, ws_bytes, match, d1,
+                              d2, stream);
+        if (st != LPSIFT_OK) break;
+        float t = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+            st = LPSIFT_EHIP;
+            break;
+        }
+        ms[c] = t / (float)reps;
+        if (c == 0 || ms[c] < best_ms) {
+            best_ms = ms[c];
+            *best = candidates[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return st;
 }
 
 }  // extern "C"

@@ -411,8 +411,11 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
             const lpsift_keypoints& kp = kps[b0 + i];
             da.img[i] = DescImg{field, im.height, im.width, kp.x, kp.y, theta[b0 + i], desc[b0 + i]};
         }
-        hipLaunchKernelGGL(polar_field_kernel, dim3((maxw + 255) / 256, maxh, nb), dim3(256), 0,
-                           stream, fa);
+        {
+            TimedScope ts(LPSIFT_KERNEL_GRADIENT, stream);
+            hipLaunchKernelGGL(polar_field_kernel, dim3((maxw + 255) / 256, maxh, nb), dim3(256), 0,
+                               stream, fa);
+        }
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
         // per-XCD band lists; the grid covers the longest one
@@ -439,6 +442,7 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
         }
         if (longest > 0) {
             const int64_t per_xcd = (longest + kWaves - 1) / kWaves;
+            TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
             hipLaunchKernelGGL(orient_describe_kernel, dim3((unsigned)(per_xcd * kXcds)),
                                dim3(64 * kWaves), 0, stream, da, tables);
             if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;

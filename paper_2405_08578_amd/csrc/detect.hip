@@ -229,7 +229,10 @@ int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,
                 base += 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
             }
         }
-        hipLaunchKernelGGL(detect_kernel, dim3(tiles), dim3(kThreads), lds, stream, a);
+        {
+            TimedScope ts(LPSIFT_KERNEL_DETECT, stream);
+            hipLaunchKernelGGL(detect_kernel, dim3(tiles), dim3(kThreads), lds, stream, a);
+        }
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
     }
     return LPSIFT_OK;

@@ -60,6 +60,22 @@ struct Geometry {
 // Validated, derived view of lpsift_params. Returns LPSIFT_OK or an error.
 int make_geometry(const lpsift_params* p, Geometry* g);
 
+// While lpsift_timing_enable(1) is in force, brackets the launches made in
+// its lifetime with HIP events on `stream`, booked under `kernel`
+// (LPSIFT_KERNEL_*); otherwise does nothing.
+class TimedScope {
+public:
+    TimedScope(int kernel, hipStream_t stream);
+    ~TimedScope();
+    TimedScope(const TimedScope&) = delete;
+    TimedScope& operator=(const TimedScope&) = delete;
+
+private:
+    int kernel_;
+    hipStream_t stream_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
 // ---- launchers (enqueue only; return LPSIFT_OK or LPSIFT_EHIP) ----
 
 int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,

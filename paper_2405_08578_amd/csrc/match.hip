@@ -1281,8 +1281,12 @@ int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStre
         hipLaunchKernelGGL(quantize_kernel<1>, gqb, dim3(256), 0, stream, B, nB, bq, sb,
                            (uint32_t*)nullptr);
         hipLaunchKernelGGL(lp_scalars_kernel, dim3(1), dim3(1), 0, stream, scal, kBf16DotErr);
-        hipLaunchKernelGGL((match_topk_lp_kernel<1, kLpKeepBf16>), grid, dim3(256), 0, stream, aq,
-                           sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
+        {
+            TimedScope ts(LPSIFT_KERNEL_MATCH_LOWP, stream);
+            hipLaunchKernelGGL((match_topk_lp_kernel<1, kLpKeepBf16>), grid, dim3(256), 0, stream,
+                               aq, sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
+        }
+        TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);
         hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepBf16>), gr, dim3(256), 0, stream, A, nA, B,
                            p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, io.match,
                            io.d1, io.d2);
@@ -1292,8 +1296,12 @@ int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStre
         hipLaunchKernelGGL(quantize_kernel<2>, gqb, dim3(256), 0, stream, B, nB, bq, sb,
                            (uint32_t*)nullptr);
         hipLaunchKernelGGL(lp_scalars_kernel, dim3(1), dim3(1), 0, stream, scal, 0.13f);
-        hipLaunchKernelGGL((match_topk_lp_kernel<2, kLpKeepFp8>), grid, dim3(256), 0, stream, aq,
-                           sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
+        {
+            TimedScope ts(LPSIFT_KERNEL_MATCH_LOWP, stream);
+            hipLaunchKernelGGL((match_topk_lp_kernel<2, kLpKeepFp8>), grid, dim3(256), 0, stream,
+                               aq, sa, nA, bq, sb, nB, nrm, scal, p.chunk_len, p.chunks, mask, keys);
+        }
+        TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);
         hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepFp8>), gr, dim3(256), 0, stream, A, nA, B,
                            p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, io.match,
                            io.d1, io.d2);
@@ -1440,22 +1448,35 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
         // the split rows' maxima are accumulated with atomics: zero them first
         if (cnt.n > 0)
             hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, 4);
-        if (rows.n > 0)
+        if (rows.n > 0) {
+            TimedScope ts(LPSIFT_KERNEL_MATCH_NORMS, stream);
             hipLaunchKernelGGL(rows_kernel, dim3((unsigned)rows_wg), dim3(256), 0, stream, rows);
-        if (main.n > 0)
+        }
+        if (main.n > 0) {
+            TimedScope ts(LPSIFT_KERNEL_MATCH_FP32, stream);
             hipLaunchKernelGGL(match_topk_f32_kernel, dim3((unsigned)main_wg), dim3(256), 0,
                                stream, main);
+        }
         if (x3.n > 0) {
-            hipLaunchKernelGGL(match_topk_x3_kernel, dim3((unsigned)x3_wg), dim3(256), 0, stream,
-                               x3);
-            hipLaunchKernelGGL(rescore_x3_kernel, dim3((unsigned)rx3_wg), dim3(256), 0, stream,
-                               rx3);
+            {
+                TimedScope ts(LPSIFT_KERNEL_MATCH_SPLIT, stream);
+                hipLaunchKernelGGL(match_topk_x3_kernel, dim3((unsigned)x3_wg), dim3(256), 0,
+                                   stream, x3);
+            }
+            {
+                TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);
+                hipLaunchKernelGGL(rescore_x3_kernel, dim3((unsigned)rx3_wg), dim3(256), 0,
+                                   stream, rx3);
+            }
+            TimedScope ts(LPSIFT_KERNEL_MATCH_REMATCH, stream);
             hipLaunchKernelGGL(match_topk_f32_kernel, dim3(strided_grid(fall_most, 1024)),
                                dim3(256), 0, stream, fall);
         }
-        if (rf.n > 0)
+        if (rf.n > 0) {
+            TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);
             hipLaunchKernelGGL(rescore_f32_kernel, dim3(strided_grid(rf_most, 8192)), dim3(256), 0,
                                stream, rf);
+        }
         if (stats && cnt.n > 0)
             hipLaunchKernelGGL(add_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, stats);
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;

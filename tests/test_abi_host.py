@@ -155,3 +155,55 @@ def test_match_validation_and_workspace(lib):
         assert lp.match_workspace_size(nA, nB, mlp) > need
         assert call(mlp) == lp.LPSIFT_ECAPACITY
     assert lp.match_workspace_size([10], [0], mp) >= 0
+
+
+def test_match_tune_validation(lib):
+    mp = lp.match_params()
+    nA, nB = [5000, 300], [4000, 0]
+    arr = lambda *v: (ctypes.c_void_p * len(v))(*v)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    needs = []
+    for c in (1, 16):
+        m = lp.match_params(b_chunks=c)
+        needs.append(lp.match_workspace_size(nA, nB, m))
+    assert needs[1] > needs[0]             # more chunks keep more candidates per query
+    ms = (ctypes.c_float * 4)()
+    best = ctypes.c_int32(0)
+
+    def call(cands, reps=2, wsb=max(needs), m=mp, msp=ms, bp=ctypes.byref(best), dA=FAKE):
+        k = len(cands)
+        return lib.lpsift_match_tune(arr(dA, FAKE), i64(*nA), arr(FAKE, FAKE), i64(*nB), 2,
+                                     ctypes.byref(m), (ctypes.c_int32 * max(k, 1))(*cands), k,
+                                     reps, 0x100000, wsb, arr(FAKE, FAKE), arr(FAKE, FAKE),
+                                     arr(FAKE, FAKE), msp, bp, None)
+    assert call([1, 16], wsb=needs[1] - 1) == lp.LPSIFT_ECAPACITY   # the largest must fit
+    assert call([0, 4]) == lp.LPSIFT_EINVAL
+    assert call([17]) == lp.LPSIFT_EINVAL
+    assert call([]) == lp.LPSIFT_EINVAL
+    assert call([2], reps=0) == lp.LPSIFT_EINVAL
+    assert call([2], msp=None) == lp.LPSIFT_EINVAL
+    assert call([2], bp=None) == lp.LPSIFT_EINVAL
+    assert call([2], dA=FAKE + 4) == lp.LPSIFT_EINVAL
+    assert call([2], m=lp.match_params(ratio=-1.0)) == lp.LPSIFT_EINVAL
+
+
+def test_tune_bucket():
+    assert [lp._bucket(n) for n in (0, 1, 2, 3, 1000, 1024, 1025)] == [0, 1, 2, 4, 1024, 1024, 2048]
+
+
+def test_timing_ids_and_validation(lib):
+    txt = open(os.path.join(ROOT, "include", "lpsift.h")).read()
+    ids = dict((m.group(1).lower(), int(m.group(2)))
+               for m in re.finditer(r"LPSIFT_KERNEL_([A-Z0-9_]+)\s*=\s*(\d+)", txt))
+    count = ids.pop("count")
+    assert len(lp.KERNELS) == count == len(ids)
+    for name, k in ids.items():
+        assert lp.KERNELS[k] == name
+    ms, n = ctypes.c_double(0), ctypes.c_int64(0)
+    assert lib.lpsift_timing_read(count, ctypes.byref(ms), ctypes.byref(n)) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_timing_read(-1, ctypes.byref(ms), ctypes.byref(n)) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_timing_read(0, None, ctypes.byref(n)) == lp.LPSIFT_EINVAL
+    lp.timing_enable(True)
+    t = lp.timing_read()            # nothing launched: no HIP call is needed
+    assert all(v["launches"] == 0 and v["ms"] == 0.0 for v in t.values())
+    lp.timing_enable(False)
