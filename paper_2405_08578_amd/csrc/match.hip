@@ -83,11 +83,15 @@ __device__ inline void block_max_atomic(uint32_t* dst, uint32_t v)
     __syncthreads();
 }
 
-// |x|^2 of the 16 rows of block blk (optional output) and the maximum over
-// rows, as the bit pattern of a non-negative float (bits order like values),
-// 16 lanes per row.
-__device__ inline void sqnorm_rows(const float* __restrict__ X, int64_t n, int64_t blk,
-                                   float* __restrict__ out, uint32_t* __restrict__ maxbits)
+// Rows per workgroup of the row passes: 16 blocks of 16 rows, so that the
+// maxima over rows cost one atomic per 256 rows.
+constexpr int kRowBlocks = 16;
+constexpr int kRowsPerWg = 16 * kRowBlocks;
+
+// |x|^2 of row blk * 16 + threadIdx.x / 16 (written to out if given), 16 lanes
+// per row; returns it (0 beyond n).
+__device__ inline float sqnorm_rows(const float* __restrict__ X, int64_t n, int64_t blk,
+                                    float* __restrict__ out)
 {
     const int64_t row = blk * 16 + threadIdx.x / 16;
     const int part = threadIdx.x % 16;
@@ -99,14 +103,20 @@ __device__ inline void sqnorm_rows(const float* __restrict__ X, int64_t n, int64
     }
     for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
     if (row < n && part == 0 && out) out[row] = s;
-    if (maxbits) block_max_atomic(maxbits, __float_as_uint(s));   // rows beyond n have s = 0
+    return s;
 }
 
+// |x|^2 of every row (optional output) and the maximum over rows, as the bit
+// pattern of a non-negative float (bits order like values); kRowsPerWg rows
+// per workgroup.
 __global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X, int64_t n,
                                                      float* __restrict__ out,
                                                      uint32_t* __restrict__ maxbits)
 {
-    sqnorm_rows(X, n, blockIdx.x, out, maxbits);
+    float m = 0.0f;
+    for (int k = 0; k < kRowBlocks; ++k)
+        m = fmaxf(m, sqnorm_rows(X, n, (int64_t)blockIdx.x * kRowBlocks + k, out));
+    if (maxbits) block_max_atomic(maxbits, __float_as_uint(m));
 }
 
 // ---------------------------------------------------------------- FP32 path --
@@ -623,8 +633,7 @@ __device__ inline void split_bf16(float x, uint32_t& hi, uint32_t& lo, float& re
 // bytes: 128 hi values, then 128 lo values, the layout of the contraction's
 // LDS tile); over rows, the maxima of |x|^2, |lo|^2 and |res|^2.
 __device__ inline void split_rows(const float* __restrict__ X, int64_t n, int64_t blk,
-                                  float* __restrict__ nrm, uint8_t* __restrict__ hl,
-                                  uint32_t* __restrict__ maxbits)
+                                  float* __restrict__ nrm, uint8_t* __restrict__ hl, float m[3])
 {
     const int64_t row = blk * 16 + threadIdx.x / 16;
     const int part = threadIdx.x % 16;
@@ -654,9 +663,9 @@ __device__ inline void split_rows(const float* __restrict__ X, int64_t n, int64_
         sr += __shfl_xor(sr, off, 16);
     }
     if (row < n && part == 0) nrm[row] = s;
-    block_max_atomic(maxbits + 0, __float_as_uint(s * 1.0001f));
-    block_max_atomic(maxbits + 1, __float_as_uint(sl * 1.0001f));
-    block_max_atomic(maxbits + 2, __float_as_uint(sr * 1.0001f));
+    m[0] = fmaxf(m[0], s);
+    m[1] = fmaxf(m[1], sl);
+    m[2] = fmaxf(m[2], sr);
 }
 
 constexpr int kX3QB = 256;          // queries per workgroup (4 waves x 2 x 32)
@@ -927,15 +936,22 @@ struct RowsBatch {
 
 __global__ __launch_bounds__(256) void rows_kernel(const RowsBatch b)
 {
-    int64_t blk;
+    int64_t wg;
     const int k = find_job(b, (int64_t)blockIdx.x,
-                           [](const RowsJob& J) { return (J.n + 15) / 16; }, blk);
+                           [](const RowsJob& J) { return (J.n + kRowsPerWg - 1) / kRowsPerWg; },
+                           wg);
     if (k < 0) return;
     const RowsJob& J = b.j[k];
-    if (J.hl)
-        split_rows(J.X, J.n, blk, J.nrm, J.hl, J.maxbits);
-    else
-        sqnorm_rows(J.X, J.n, blk, J.nrm, nullptr);
+    if (J.hl) {
+        float m[3] = {0.0f, 0.0f, 0.0f};
+        for (int r = 0; r < kRowBlocks; ++r) split_rows(J.X, J.n, wg * kRowBlocks + r, J.nrm, J.hl, m);
+        // 1.0001: margin for the FP32 rounding of the sums
+        block_max_atomic(J.maxbits + 0, __float_as_uint(m[0] * 1.0001f));
+        block_max_atomic(J.maxbits + 1, __float_as_uint(m[1] * 1.0001f));
+        block_max_atomic(J.maxbits + 2, __float_as_uint(m[2] * 1.0001f));
+    } else {
+        for (int r = 0; r < kRowBlocks; ++r) sqnorm_rows(J.X, J.n, wg * kRowBlocks + r, J.nrm);
+    }
 }
 
 // FP32 contraction with top-2 per lane. Items of a job are (chunk, query
@@ -1271,10 +1287,12 @@ int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStre
     const uint32_t mask = idx_mask_for(p.chunk_len);
     const dim3 grid((unsigned)((nA + kLpQB - 1) / kLpQB), (unsigned)p.chunks);
     const dim3 gq((unsigned)((nA + 15) / 16)), gqb((unsigned)((nB + 15) / 16));
+    const dim3 gn((unsigned)((nA + kRowsPerWg - 1) / kRowsPerWg));
+    const dim3 gnb((unsigned)((nB + kRowsPerWg - 1) / kRowsPerWg));
 
     hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(64), 0, stream, counters, 4);
-    hipLaunchKernelGGL(sqnorm_kernel, gq, dim3(256), 0, stream, A, nA, (float*)nullptr, counters + 1);
-    hipLaunchKernelGGL(sqnorm_kernel, gqb, dim3(256), 0, stream, B, nB, nrm, counters + 2);
+    hipLaunchKernelGGL(sqnorm_kernel, gn, dim3(256), 0, stream, A, nA, (float*)nullptr, counters + 1);
+    hipLaunchKernelGGL(sqnorm_kernel, gnb, dim3(256), 0, stream, B, nB, nrm, counters + 2);
     if (mp->precision == 1) {
         hipLaunchKernelGGL(quantize_kernel<1>, gq, dim3(256), 0, stream, A, nA, aq, sa,
                            (uint32_t*)nullptr);
@@ -1419,7 +1437,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
             if (owner[i] == i) {
                 rows.j[rows.n++] = RowsJob{P.B, Q.nrm, mp->precision == 3 ? Q.bhl : nullptr,
                                            Q.cnt ? Q.cnt + 1 : nullptr, P.nB};
-                rows_wg += (P.nB + 15) / 16;
+                rows_wg += (P.nB + kRowsPerWg - 1) / kRowsPerWg;
             }
             if (mp->precision == 0) {
                 main.j[main.n++] = F32Job{P.A, nullptr, nullptr, P.B, O.nrm, Q.fidx, Q.fscore,
