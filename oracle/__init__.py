@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline import this package; the product library never does, and the oracle
 never imports the product. The arithmetic lives in ``lpsift_oracle.c`` (plain
-C, double precision) and ``ransac.py`` (NumPy, double precision); this module
-only marshals arrays.
+C, double precision), ``ransac.py`` and ``scorer.py`` (NumPy, double
+precision); this module only marshals arrays.
 
 Pins (what each function is checked against, in tests/test_oracle_*.py):
   detect       brute force on tiny images, Eq. 1 in exact rational arithmetic,
@@ -15,6 +15,9 @@ Pins (what each function is checked against, in tests/test_oracle_*.py):
                binning of a ramp, rotation and gain invariance, unit norm
   match        SciPy k-d tree / cdist cross-check, hand-built exact cases
   ransac       exact correspondences (DLT recovers H), known outlier sets
+  scorer       padded-slice patches, torch FP64 autograd and finite
+               differences for the MLP gradient, Adam's closed-form first
+               step and torch's Adam, brute-force sort for the prune
 """
 from __future__ import annotations
 

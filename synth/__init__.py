@@ -345,3 +345,18 @@ def ransac_samples(n_points: int, n_iter: int, rng: np.random.Generator) -> np.n
     for i in range(n_iter):
         out[i] = rng.choice(n_points, 4, replace=False)
     return out
+
+
+def scorer_init(rng: np.random.Generator, n_in: int = 258, n_hid: int = 64) -> np.ndarray:
+    """Seeded starting weights of the keypoint scorer as one flat float64
+    vector in the order W1 [n_hid][n_in], b1, W2 [n_hid][n_hid], b2, w3, b3:
+    weights uniform in +-sqrt(6 / fan_in), biases zero."""
+    parts = []
+    for fan_in, shape in ((n_in, (n_hid, n_in)), (0, (n_hid,)), (n_hid, (n_hid, n_hid)),
+                          (0, (n_hid,)), (n_hid, (n_hid,)), (0, (1,))):
+        if fan_in == 0:
+            parts.append(np.zeros(int(np.prod(shape))))
+        else:
+            lim = math.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-lim, lim, int(np.prod(shape))))
+    return np.concatenate(parts)
