@@ -53,8 +53,18 @@ enum lpsift_kernel {
     LPSIFT_KERNEL_MATCH_RESCORE = 6,   /* FP32 rescore + ratio test (all precisions) */
     LPSIFT_KERNEL_MATCH_REMATCH = 7,   /* FP32 re-match of uncertified split queries */
     LPSIFT_KERNEL_MATCH_LOWP = 8,      /* BF16 / FP8 contraction with top-k */
-    LPSIFT_KERNEL_COUNT = 9
+    LPSIFT_KERNEL_SCORE = 9,           /* learned scorer inference */
+    LPSIFT_KERNEL_PRUNE = 10,          /* top-k selection of keypoint slots */
+    LPSIFT_KERNEL_TRAIN = 11,          /* scorer training step (both kernels) */
+    LPSIFT_KERNEL_COUNT = 12
 };
+
+/* Learned keypoint scorer: MLP 258 -> 64 -> 64 -> 1 (ReLU), parameters as one
+ * FP32 vector in the order W1 [64][258], b1 [64], W2 [64][64], b2 [64],
+ * w3 [64], b3 [1]. */
+#define LPSIFT_SCORER_IN 258
+#define LPSIFT_SCORER_HID 64
+#define LPSIFT_SCORER_PARAMS 20801
 
 /* Method parameters (Sec. 2.2-2.3).
  *  n_scales  number of window sizes, 1..LPSIFT_MAX_SCALES
@@ -179,6 +189,68 @@ size_t lpsift_describe_workspace_size(const lpsift_image* imgs, int32_t n_images
 int lpsift_describe(const lpsift_image* imgs, int32_t n_images, const lpsift_keypoints* kps,
                     const lpsift_params* params, void* workspace, size_t ws_bytes,
                     float* const* theta, float* const* desc, void* stream);
+
+/* lpsift_describe for listed keypoint slots only: for each image i, slots
+ * sel[i][0 .. n_sel[i]) (device int32, each in [0, lpsift_num_keypoints)) are
+ * described exactly as lpsift_describe does and written compacted:
+ * theta[i][k], desc[i][k*128 ..] for list entry k. An entry naming no slot of
+ * the image gets a zero descriptor and a NaN orientation. Same workspace as
+ * lpsift_describe. Errors as lpsift_describe, plus EINVAL for a null or
+ * negative list. */
+int lpsift_describe_selected(const lpsift_image* imgs, int32_t n_images,
+                             const lpsift_keypoints* kps, const lpsift_params* params,
+                             const int32_t* const* sel, const int64_t* n_sel, void* workspace,
+                             size_t ws_bytes, float* const* theta, float* const* desc,
+                             void* stream);
+
+/* Learned keypoint scorer (not part of the paper's method; it ranks the
+ * keypoints of Sec. 2.2 so that only the best share is described and matched).
+ * Features of a keypoint at (x, y), 258 values: the 16 x 16 patch
+ * I(y + r - 8, x + c - 8) / 255 at index 16 r + c (0 outside the image), then
+ * (log2 L_s - log2 L_min) / (log2 L_max - log2 L_min) of its window size (0
+ * with one scale), then its contrast. The score is the MLP's output logit
+ * z = w3 . relu(W2 relu(W1 x + b1) + b2) + b3.
+ *
+ * lpsift_score: scores[i][slot] for every keypoint slot written by
+ * lpsift_detect. weights: device FP32 [LPSIFT_SCORER_PARAMS]; W1 and W2 are
+ * rounded to BF16 for the matrix cores (FP32 accumulation), and h1 to BF16 as
+ * the second layer's input. Errors: EINVAL, ECAPACITY (keypoint capacity),
+ * EUNSUPPORTED, EHIP. */
+int lpsift_score(const lpsift_image* imgs, int32_t n_images, const lpsift_keypoints* kps,
+                 const lpsift_params* params, const float* weights, float* const* scores,
+                 void* stream);
+
+/* Top-k prune: for each image i, the k[i] slots with the largest scores
+ * scores[i][0 .. n[i]) (larger score first, lower slot on ties; NaN ranks
+ * lowest), written to sel[i][0 .. k[i]) in ascending slot order. Host arrays
+ * n, k, and of device pointers scores, sel. Errors: EINVAL (k > n, negative
+ * counts, null pointers), EHIP. */
+int lpsift_prune(const float* const* scores, const int64_t* n, const int64_t* k,
+                 int32_t n_images, int32_t* const* sel, void* stream);
+
+/* Training records of keypoints: for list entry e of image i (sel null: every
+ * slot), patches[i][e*256 ..] = the uint8 16 x 16 patch (0 outside the image)
+ * and extra[i][2e], extra[i][2e+1] = the scale feature and the contrast.
+ * patches must be 4-byte aligned. Errors: EINVAL, ECAPACITY, EHIP. */
+int lpsift_scorer_gather(const lpsift_image* imgs, int32_t n_images, const lpsift_keypoints* kps,
+                         const lpsift_params* params, const int32_t* const* sel,
+                         const int64_t* n_sel, uint8_t* const* patches, float* const* extra,
+                         void* stream);
+
+/* Device workspace of lpsift_scorer_train_step for a batch (0 if batch < 1). */
+size_t lpsift_scorer_train_workspace_size(int64_t batch);
+
+/* One training step of the scorer on a batch of records: loss = sum_c
+ * cweight[c] BCE(sigmoid(z_c), labels[c]) / sum_c cweight[c], gradients by
+ * backpropagation in FP32 (deterministic: fixed-order sums), then Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step t >= 1) on the
+ * FP32 weights and moments adam_m, adam_v (device [LPSIFT_SCORER_PARAMS],
+ * zero before the first step). loss: optional device float receiving the
+ * batch loss at the weights before the step. Errors: EINVAL, ECAPACITY, EHIP. */
+int lpsift_scorer_train_step(const uint8_t* patches, const float* extra, const float* labels,
+                             const float* cweight, int64_t batch, float* weights, float* adam_m,
+                             float* adam_v, int64_t step, float lr, void* workspace,
+                             size_t ws_bytes, float* loss, void* stream);
 
 /* Device workspace, in bytes, that lpsift_match needs. nA, nB: host arrays of
  * n_pairs descriptor counts. */

@@ -54,7 +54,8 @@ class lpsift_match_params(ctypes.Structure):
 EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
            "lpsift_describe_workspace_size", "lpsift_describe", "lpsift_match_workspace_size",
            "lpsift_match", "lpsift_match_tune", "lpsift_timing_enable", "lpsift_timing_read",
-           "lpsift_ransac_host")
+           "lpsift_describe_selected", "lpsift_score", "lpsift_prune", "lpsift_scorer_gather",
+           "lpsift_scorer_train_workspace_size", "lpsift_scorer_train_step", "lpsift_ransac_host")
 
 _lib = None
 
@@ -103,6 +104,24 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_timing_enable.argtypes = [c_i32]
     lib.lpsift_timing_read.restype = ctypes.c_int
     lib.lpsift_timing_read.argtypes = [c_i32, P(c_f64), P(c_i64)]
+    lib.lpsift_describe_selected.restype = ctypes.c_int
+    lib.lpsift_describe_selected.argtypes = [P(lpsift_image), c_i32, P(lpsift_keypoints),
+                                             P(lpsift_params), P(c_vp), P(c_i64), c_vp,
+                                             ctypes.c_size_t, P(c_vp), P(c_vp), c_vp]
+    lib.lpsift_score.restype = ctypes.c_int
+    lib.lpsift_score.argtypes = [P(lpsift_image), c_i32, P(lpsift_keypoints), P(lpsift_params),
+                                 c_vp, P(c_vp), c_vp]
+    lib.lpsift_prune.restype = ctypes.c_int
+    lib.lpsift_prune.argtypes = [P(c_vp), P(c_i64), P(c_i64), c_i32, P(c_vp), c_vp]
+    lib.lpsift_scorer_gather.restype = ctypes.c_int
+    lib.lpsift_scorer_gather.argtypes = [P(lpsift_image), c_i32, P(lpsift_keypoints),
+                                         P(lpsift_params), P(c_vp), P(c_i64), P(c_vp), P(c_vp),
+                                         c_vp]
+    lib.lpsift_scorer_train_workspace_size.restype = ctypes.c_size_t
+    lib.lpsift_scorer_train_workspace_size.argtypes = [c_i64]
+    lib.lpsift_scorer_train_step.restype = ctypes.c_int
+    lib.lpsift_scorer_train_step.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp,
+                                             c_i64, c_f32, c_vp, ctypes.c_size_t, c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -359,7 +378,115 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
 
 
 KERNELS = ("detect", "gradient", "describe", "match_norms", "match_fp32", "match_split",
-           "match_rescore", "match_rematch", "match_lowp")
+           "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train")
+SCORER_PARAMS = 20801
+
+
+def describe_selected(images, kps, params: Params, sel, workspace=None, theta=None, desc=None,
+                      stream=None):
+    """Orientation and descriptor of the listed slots sel[i] (int32 CUDA
+    tensors) of each image, compacted in list order."""
+    import torch
+    lib = load()
+    imgs = _images(images)
+    dev = images[0].device
+    n = len(images)
+    ns = [int(s.numel()) for s in sel]
+    if theta is None:
+        theta = [torch.empty(m, dtype=torch.float32, device=dev) for m in ns]
+    if desc is None:
+        desc = [torch.empty((m, DESC_DIM), dtype=torch.float32, device=dev) for m in ns]
+    p = params.c()
+    need = int(lib.lpsift_describe_workspace_size(imgs, n, ctypes.byref(p)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check("lpsift_describe_selected", lib.lpsift_describe_selected(
+        imgs, n, _kps(kps), ctypes.byref(p), (c_vp * n)(*[s.data_ptr() for s in sel]),
+        (c_i64 * n)(*ns), workspace.data_ptr(), workspace.numel(),
+        (c_vp * n)(*[t.data_ptr() for t in theta]), (c_vp * n)(*[t.data_ptr() for t in desc]),
+        _stream(stream)))
+    return theta, desc
+
+
+def score(images, kps, params: Params, weights, out=None, stream=None):
+    """Scorer logits of every keypoint slot (weights: FP32 CUDA tensor [20801])."""
+    import torch
+    lib = load()
+    n = len(images)
+    if weights.dtype != torch.float32 or weights.numel() != SCORER_PARAMS or not weights.is_cuda:
+        raise ValueError("weights must be a float32 CUDA tensor of 20801 values")
+    if out is None:
+        out = [torch.empty(kp["x"].numel(), dtype=torch.float32, device=weights.device)
+               for kp in kps]
+    _check("lpsift_score", lib.lpsift_score(
+        _images(images), n, _kps(kps), ctypes.byref(params.c()), weights.data_ptr(),
+        (c_vp * n)(*[t.data_ptr() for t in out]), _stream(stream)))
+    return out
+
+
+def keep_count(n: int, num: int = 3, den: int = 10) -> int:
+    """ceil(n num / den) in integers (30 % by default)."""
+    return -(-int(n) * num // den)
+
+
+def prune(scores, k: Sequence[int], out=None, stream=None):
+    """Ascending slots of the k[i] best scores of each image (int32 tensors)."""
+    import torch
+    lib = load()
+    n = len(scores)
+    if out is None:
+        out = [torch.empty(int(kk), dtype=torch.int32, device=s.device) for s, kk in zip(scores, k)]
+    _check("lpsift_prune", lib.lpsift_prune(
+        (c_vp * n)(*[s.data_ptr() for s in scores]), (c_i64 * n)(*[s.numel() for s in scores]),
+        (c_i64 * n)(*[int(x) for x in k]), n, (c_vp * n)(*[t.data_ptr() for t in out]),
+        _stream(stream)))
+    return out
+
+
+def scorer_gather(images, kps, params: Params, sel=None, stream=None):
+    """uint8 patches [m, 256] and float extras [m, 2] of listed (or all) slots."""
+    import torch
+    lib = load()
+    n = len(images)
+    dev = images[0].device
+    ms = [int(s.numel()) for s in sel] if sel is not None else \
+        [num_keypoints(t.shape[0], t.shape[1], params) for t in images]
+    patches = [torch.empty((m, 256), dtype=torch.uint8, device=dev) for m in ms]
+    extra = [torch.empty((m, 2), dtype=torch.float32, device=dev) for m in ms]
+    sel_arr = None if sel is None else (c_vp * n)(*[s.data_ptr() for s in sel])
+    n_arr = None if sel is None else (c_i64 * n)(*ms)
+    _check("lpsift_scorer_gather", lib.lpsift_scorer_gather(
+        _images(images), n, _kps(kps), ctypes.byref(params.c()), sel_arr, n_arr,
+        (c_vp * n)(*[t.data_ptr() for t in patches]), (c_vp * n)(*[t.data_ptr() for t in extra]),
+        _stream(stream)))
+    return patches, extra
+
+
+class ScorerTrainer:
+    """Device state of scorer training: FP32 weights, Adam moments, workspace."""
+
+    def __init__(self, weights, batch: int):
+        import torch
+        self.weights = weights
+        self.m = torch.zeros_like(weights)
+        self.v = torch.zeros_like(weights)
+        self.batch = int(batch)
+        need = int(load().lpsift_scorer_train_workspace_size(self.batch))
+        self.ws = torch.empty(max(need, 4), dtype=torch.uint8, device=weights.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=weights.device)
+        self.t = 0
+
+    def step(self, patches, extra, labels, cweight, lr: float, stream=None):
+        """One Adam step on a batch (<= the batch size given at construction);
+        self.loss holds the batch loss before the step."""
+        b = int(labels.numel())
+        if b > self.batch:
+            raise ValueError("batch larger than the trainer's workspace")
+        self.t += 1
+        _check("lpsift_scorer_train_step", load().lpsift_scorer_train_step(
+            patches.data_ptr(), extra.data_ptr(), labels.data_ptr(), cweight.data_ptr(), b,
+            self.weights.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.t, float(lr),
+            self.ws.data_ptr(), self.ws.numel(), self.loss.data_ptr(), _stream(stream)))
 
 
 def timing_enable(on: bool = True):

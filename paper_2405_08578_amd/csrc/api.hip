@@ -158,8 +158,155 @@ int lpsift_describe(const lpsift_image* imgs, int32_t n, const lpsift_keypoints*
     if (st != LPSIFT_OK) return st;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
     if (ws_bytes < describe_workspace_bytes(imgs, n, g)) return LPSIFT_ECAPACITY;
-    return launch_describe(imgs, n, kps, g, workspace, theta, desc,
+    return launch_describe(imgs, n, kps, g, workspace, theta, desc, nullptr, nullptr,
                            static_cast<hipStream_t>(stream));
+}
+
+int lpsift_describe_selected(const lpsift_image* imgs, int32_t n, const lpsift_keypoints* kps,
+                             const lpsift_params* p, const int32_t* const* sel,
+                             const int64_t* n_sel, void* workspace, size_t ws_bytes,
+                             float* const* theta, float* const* desc, void* stream)
+{
+    Geometry g;
+    int st = make_geometry(p, &g);
+    if (st == LPSIFT_EINVAL) return st;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    if (!theta || !desc || !workspace || !sel || !n_sel) return LPSIFT_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (n_sel[i] < 0 || n_sel[i] > INT32_MAX) return LPSIFT_EINVAL;
+        if (n_sel[i] > 0 && (!sel[i] || !theta[i] || !desc[i])) return LPSIFT_EINVAL;
+    }
+    const int stk = check_keypoints(imgs, n, kps, p);
+    if (stk != LPSIFT_OK) return stk;
+    if (st != LPSIFT_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    if (ws_bytes < describe_workspace_bytes(imgs, n, g)) return LPSIFT_ECAPACITY;
+    return launch_describe(imgs, n, kps, g, workspace, theta, desc, sel, n_sel,
+                           static_cast<hipStream_t>(stream));
+}
+
+// normalised log2 window size per scale (feature 256 of the scorer)
+static void scale_features(const lpsift_params* p, float* out)
+{
+    const double l0 = std::log2((double)p->L[0]);
+    const double l1 = std::log2((double)p->L[p->n_scales - 1]);
+    for (int s = 0; s < LPSIFT_MAX_SCALES; ++s) {
+        out[s] = 0.0f;
+        if (s < p->n_scales && p->n_scales > 1)
+            out[s] = (float)((std::log2((double)p->L[s]) - l0) / (l1 - l0));
+    }
+}
+
+int lpsift_score(const lpsift_image* imgs, int32_t n, const lpsift_keypoints* kps,
+                 const lpsift_params* p, const float* weights, float* const* scores, void* stream)
+{
+    Geometry g;
+    int st = make_geometry(p, &g);
+    if (st == LPSIFT_EINVAL) return st;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    if (!weights || !scores) return LPSIFT_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!scores[i]) return LPSIFT_EINVAL;
+    const int stk = check_keypoints(imgs, n, kps, p);
+    if (stk != LPSIFT_OK) return stk;
+    if (st != LPSIFT_OK) return st;
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = (n - b0 < kMaxBatch) ? n - b0 : kMaxBatch;
+        ScoreArgs a{};
+        a.n_images = nb;
+        scale_features(p, a.sfeat);
+        for (int i = 0; i < nb; ++i) {
+            const lpsift_image& im = imgs[b0 + i];
+            const lpsift_keypoints& k = kps[b0 + i];
+            a.img[i] = ScoreImg{im.data, im.pitch, im.height, im.width, k.x, k.y, k.scale,
+                                k.contrast, scores[b0 + i],
+                                lpsift_num_keypoints(im.height, im.width, p)};
+        }
+        const int r = launch_score(a, weights, static_cast<hipStream_t>(stream));
+        if (r != LPSIFT_OK) return r;
+    }
+    return LPSIFT_OK;
+}
+
+int lpsift_prune(const float* const* scores, const int64_t* n, const int64_t* k,
+                 int32_t n_images, int32_t* const* sel, void* stream)
+{
+    if (!scores || !n || !k || !sel || n_images < 1) return LPSIFT_EINVAL;
+    for (int i = 0; i < n_images; ++i) {
+        if (n[i] < 0 || n[i] > INT32_MAX || k[i] < 0 || k[i] > n[i]) return LPSIFT_EINVAL;
+        if (n[i] > 0 && !scores[i]) return LPSIFT_EINVAL;
+        if (k[i] > 0 && !sel[i]) return LPSIFT_EINVAL;
+    }
+    for (int b0 = 0; b0 < n_images; b0 += kMaxBatch) {
+        const int nb = (n_images - b0 < kMaxBatch) ? n_images - b0 : kMaxBatch;
+        PruneArgs a{};
+        a.n_images = nb;
+        for (int i = 0; i < nb; ++i)
+            a.img[i] = PruneImg{scores[b0 + i], n[b0 + i], k[b0 + i], sel[b0 + i]};
+        const int r = launch_prune(a, static_cast<hipStream_t>(stream));
+        if (r != LPSIFT_OK) return r;
+    }
+    return LPSIFT_OK;
+}
+
+int lpsift_scorer_gather(const lpsift_image* imgs, int32_t n, const lpsift_keypoints* kps,
+                         const lpsift_params* p, const int32_t* const* sel, const int64_t* n_sel,
+                         uint8_t* const* patches, float* const* extra, void* stream)
+{
+    Geometry g;
+    const int st = make_geometry(p, &g);
+    if (st == LPSIFT_EINVAL) return st;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    if (!patches || !extra) return LPSIFT_EINVAL;
+    const int stk = check_keypoints(imgs, n, kps, p);
+    if (stk != LPSIFT_OK) return stk;
+    for (int i = 0; i < n; ++i) {
+        const int64_t cnt = sel ? (n_sel ? n_sel[i] : -1)
+                                : lpsift_num_keypoints(imgs[i].height, imgs[i].width, p);
+        if (cnt < 0 || cnt > INT32_MAX) return LPSIFT_EINVAL;
+        if (cnt > 0 && (!patches[i] || !extra[i] || (sel && !sel[i]))) return LPSIFT_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(patches[i]) & 3u) != 0) return LPSIFT_EINVAL;
+    }
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = (n - b0 < kMaxBatch) ? n - b0 : kMaxBatch;
+        GatherArgs a{};
+        a.n_images = nb;
+        scale_features(p, a.sfeat);
+        for (int i = 0; i < nb; ++i) {
+            const lpsift_image& im = imgs[b0 + i];
+            const lpsift_keypoints& k = kps[b0 + i];
+            const int64_t nkp = lpsift_num_keypoints(im.height, im.width, p);
+            a.img[i] = GatherImg{im.data, im.pitch, im.height, im.width, k.x, k.y, k.scale,
+                                 k.contrast, sel ? sel[b0 + i] : nullptr,
+                                 sel ? n_sel[b0 + i] : nkp, nkp, patches[b0 + i], extra[b0 + i]};
+        }
+        const int r = launch_gather(a, static_cast<hipStream_t>(stream));
+        if (r != LPSIFT_OK) return r;
+    }
+    return LPSIFT_OK;
+}
+
+size_t lpsift_scorer_train_workspace_size(int64_t batch)
+{
+    return batch < 1 ? 0 : train_workspace_bytes(batch);
+}
+
+int lpsift_scorer_train_step(const uint8_t* patches, const float* extra, const float* labels,
+                             const float* cweight, int64_t batch, float* weights, float* adam_m,
+                             float* adam_v, int64_t step, float lr, void* workspace,
+                             size_t ws_bytes, float* loss, void* stream)
+{
+    if (!patches || !extra || !labels || !cweight || !weights || !adam_m || !adam_v ||
+        !workspace || batch < 1 || batch > (int64_t)1 << 26 || step < 1 ||
+        !(lr > 0.0f) || !std::isfinite(lr))
+        return LPSIFT_EINVAL;
+    if (ws_bytes < train_workspace_bytes(batch)) return LPSIFT_ECAPACITY;
+    TrainArgs a{patches, extra, labels, cweight, batch, weights, adam_m, adam_v,
+                static_cast<float*>(workspace), loss, step, lr};
+    return launch_train(a, static_cast<hipStream_t>(stream));
 }
 
 static int check_match_params(const lpsift_match_params* mp)

@@ -127,11 +127,15 @@ struct DescImg {
     const int32_t* y;
     float* theta;
     float* desc;
+    const int32_t* sel;    // list mode: slots to describe, outputs compacted
+    int64_t n_sel;
+    int64_t n_kp;          // slots of the image
 };
 
 struct DescArgs {   // passed by value: keep well under 4 KB
     int32_t n_images;
     int32_t n_scales;
+    int32_t list;          // 1: describe img[i].sel[0 .. n_sel) only
     ScaleGeom geom[LPSIFT_MAX_SCALES];
     int32_t L[LPSIFT_MAX_SCALES];
     // first slot of scale s in image i
@@ -181,27 +185,52 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long* hist = hist_all[wave];
 
-    // locate (scale, image, slot) of this wave's keypoint in its XCD's band list
-    const int xcd = blockIdx.x % kXcds;
-    int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + wave;
-    bool live = false;
+    bool live = false, has_out = false;
     int sc = 0, im = 0;
-    int64_t slot = 0;
-    for (int so = 0; so < a.n_scales && !live; ++so) {
-        const int s = a.n_scales - 1 - so;
+    int64_t slot = 0, out_at = 0;
+    if (a.list) {
+        // list mode: entries of every image in turn, each list from its end
+        // (largest slots, i.e. largest scale, first); output at the entry
+        int64_t j = (int64_t)blockIdx.x * kWaves + wave;
         for (int i = 0; i < a.n_images; ++i) {
-            const int64_t nby = n_windows(a.img[i].h, a.L[s]), nbx = n_windows(a.img[i].w, a.L[s]);
-            const int64_t cnt = band_items(xcd, nby, nbx);
-            if (j < cnt) {
-                live = true;
-                sc = s;
+            if (j < a.img[i].n_sel) {
                 im = i;
-                slot = a.slot_base[s][i] + 2 * ((xcd * nby) / kXcds) * nbx + j;
+                has_out = true;
+                out_at = a.img[i].n_sel - 1 - j;
+                slot = a.img[i].sel[out_at];
+                live = slot >= 0 && slot < a.img[i].n_kp;
+                for (int s = a.n_scales - 1; s >= 0; --s)
+                    if (slot >= a.slot_base[s][i]) {
+                        sc = s;
+                        break;
+                    }
                 break;
             }
-            j -= cnt;
+            j -= a.img[i].n_sel;
         }
+    } else {
+        // locate (scale, image, slot) of this wave's keypoint in its XCD's band list
+        const int xcd = blockIdx.x % kXcds;
+        int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + wave;
+        for (int so = 0; so < a.n_scales && !live; ++so) {
+            const int s = a.n_scales - 1 - so;
+            for (int i = 0; i < a.n_images; ++i) {
+                const int64_t nby = n_windows(a.img[i].h, a.L[s]), nbx = n_windows(a.img[i].w, a.L[s]);
+                const int64_t cnt = band_items(xcd, nby, nbx);
+                if (j < cnt) {
+                    live = true;
+                    sc = s;
+                    im = i;
+                    slot = a.slot_base[s][i] + 2 * ((xcd * nby) / kXcds) * nbx + j;
+                    break;
+                }
+                j -= cnt;
+            }
+        }
+        has_out = live;
+        out_at = slot;
     }
+    if (!live) slot = 0;
     const DescImg& I = a.img[im];
     const ScaleGeom& G = a.geom[sc];
     const int kx = I.x[slot], ky = I.y[slot];
@@ -276,7 +305,7 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     const float den = hm - 2.0f * bv + hp;
     const float offp = (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
     const float th_turns = ((float)bk + offp) / 36.0f;
-    if (live && lane == 0) I.theta[slot] = th_turns * 6.283185307179586f;
+    if (live && lane == 0) I.theta[out_at] = th_turns * 6.283185307179586f;
 
     // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
     float sn, cs;
@@ -352,9 +381,14 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     d1 = fminf(d1 / nrm, 0.2f);
     nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
     if (live) {
-        float* out = I.desc + slot * 128;
+        float* out = I.desc + out_at * 128;
         out[lane] = d0 / nrm;
         out[lane + 64] = d1 / nrm;
+    } else if (has_out) {   // list entry naming no slot of the image
+        float* out = I.desc + out_at * 128;
+        out[lane] = 0.0f;
+        out[lane + 64] = 0.0f;
+        if (lane == 0) I.theta[out_at] = __builtin_nanf("");
     }
 }
 
@@ -375,7 +409,7 @@ size_t describe_workspace_bytes(const lpsift_image* imgs, int n, const Geometry&
 
 int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
                     const Geometry& g, void* ws, float* const* theta, float* const* desc,
-                    hipStream_t stream)
+                    const int32_t* const* sel, const int64_t* n_sel, hipStream_t stream)
 {
     char* base = static_cast<char*>(ws);
     int32_t* tables = reinterpret_cast<int32_t*>(base);
@@ -409,7 +443,11 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
             maxw = im.width > maxw ? im.width : maxw;
             maxh = im.height > maxh ? im.height : maxh;
             const lpsift_keypoints& kp = kps[b0 + i];
-            da.img[i] = DescImg{field, im.height, im.width, kp.x, kp.y, theta[b0 + i], desc[b0 + i]};
+            int64_t n_kp = 0;
+            for (int s = 0; s < g.n_scales; ++s)
+                n_kp += 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
+            da.img[i] = DescImg{field, im.height, im.width, kp.x, kp.y, theta[b0 + i], desc[b0 + i],
+                                sel ? sel[b0 + i] : nullptr, sel ? n_sel[b0 + i] : 0, n_kp};
         }
         {
             TimedScope ts(LPSIFT_KERNEL_GRADIENT, stream);
@@ -418,6 +456,7 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
         }
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
+        da.list = sel ? 1 : 0;
         // per-XCD band lists; the grid covers the longest one
         int64_t longest = 0;
         for (int s = 0; s < g.n_scales; ++s) {
@@ -440,7 +479,17 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
                                         n_windows(imgs[b0 + i].width, g.L[s]));
             longest = items > longest ? items : longest;
         }
-        if (longest > 0) {
+        if (sel) {
+            int64_t entries = 0;
+            for (int i = 0; i < nb; ++i) entries += n_sel[b0 + i];
+            if (entries > 0) {
+                TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
+                hipLaunchKernelGGL(orient_describe_kernel,
+                                   dim3((unsigned)((entries + kWaves - 1) / kWaves)),
+                                   dim3(64 * kWaves), 0, stream, da, tables);
+                if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+            }
+        } else if (longest > 0) {
             const int64_t per_xcd = (longest + kWaves - 1) / kWaves;
             TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
             hipLaunchKernelGGL(orient_describe_kernel, dim3((unsigned)(per_xcd * kXcds)),

@@ -84,9 +84,11 @@ int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,
 // Workspace layout of describe: disc tables, then one float2 gradient field
 // per image (8 bytes per pixel), each 256-byte aligned.
 size_t describe_workspace_bytes(const lpsift_image* imgs, int n, const Geometry& g);
+// sel / n_sel (host arrays, or null for every slot): describe only the listed
+// slots of each image, outputs compacted in list order.
 int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
                     const Geometry& g, void* ws, float* const* theta, float* const* desc,
-                    hipStream_t s);
+                    const int32_t* const* sel, const int64_t* n_sel, hipStream_t s);
 
 struct MatchPlan {
     int chunks;          // candidate-range split
@@ -111,5 +113,75 @@ struct MatchPairIO {
 // launch and compute the norms of a candidate set shared by several pairs once.
 int launch_match_pairs(const MatchPairIO* pairs, int n, const lpsift_match_params* mp,
                        hipStream_t s);
+
+// ---- learned keypoint scorer ----
+
+struct ScoreImg {
+    const uint8_t* data;
+    int64_t pitch;
+    int32_t h, w;
+    const int32_t* x;
+    const int32_t* y;
+    const uint8_t* scale;
+    const float* contrast;
+    float* score;
+    int64_t n;             // keypoints (all slots)
+};
+struct ScoreArgs {
+    int32_t n_images;
+    float sfeat[LPSIFT_MAX_SCALES];   // normalised log2 window size per scale
+    ScoreImg img[kMaxBatch];
+};
+int launch_score(const ScoreArgs& args, const float* weights, hipStream_t s);
+
+struct PruneImg {
+    const float* score;
+    int64_t n;
+    int64_t k;
+    int32_t* sel;
+};
+struct PruneArgs {
+    int32_t n_images;
+    PruneImg img[kMaxBatch];
+};
+int launch_prune(const PruneArgs& args, hipStream_t s);
+
+struct GatherImg {
+    const uint8_t* data;
+    int64_t pitch;
+    int32_t h, w;
+    const int32_t* x;
+    const int32_t* y;
+    const uint8_t* scale;
+    const float* contrast;
+    const int32_t* sel;    // slots to gather (null: all slots)
+    int64_t n;             // entries
+    int64_t n_kp;          // slots of the image (bound for sel)
+    uint8_t* patches;      // [n][256]
+    float* extra;          // [n][2]
+};
+struct GatherArgs {
+    int32_t n_images;
+    float sfeat[LPSIFT_MAX_SCALES];
+    GatherImg img[kMaxBatch];
+};
+int launch_gather(const GatherArgs& args, hipStream_t s);
+
+struct TrainArgs {
+    const uint8_t* patches;   // [batch][256]
+    const float* extra;       // [batch][2]
+    const float* labels;      // [batch]
+    const float* cweight;     // [batch]
+    int64_t batch;
+    float* weights;           // FP32 master, updated
+    float* adam_m;
+    float* adam_v;
+    float* partials;          // workspace
+    float* loss;              // optional
+    int64_t step;
+    float lr;
+};
+size_t train_workspace_bytes(int64_t batch);
+int launch_train(TrainArgs args, hipStream_t s);
 
 }  // namespace lpsift

@@ -207,3 +207,49 @@ def test_timing_ids_and_validation(lib):
     t = lp.timing_read()            # nothing launched: no HIP call is needed
     assert all(v["launches"] == 0 and v["ms"] == 0.0 for v in t.values())
     lp.timing_enable(False)
+
+
+def test_scorer_entry_validation(lib):
+    P = lp.Params([16, 32]).c()
+    n = lp.num_keypoints(64, 64, lp.Params([16, 32]))
+    ims = (lp.lpsift_image * 1)(image())
+    ks = (lp.lpsift_keypoints * 1)(kps(n))
+    arr = lambda *v: (ctypes.c_void_p * len(v))(*v)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    # score
+    assert lib.lpsift_score(ims, 1, ks, ctypes.byref(P), None, arr(FAKE), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_score(ims, 1, ks, ctypes.byref(P), FAKE, arr(None), None) == lp.LPSIFT_EINVAL
+    small = (lp.lpsift_keypoints * 1)(kps(n - 1))
+    assert lib.lpsift_score(ims, 1, small, ctypes.byref(P), FAKE, arr(FAKE), None) \
+        == lp.LPSIFT_ECAPACITY
+    # prune: k <= n, non-negative, pointers
+    assert lib.lpsift_prune(arr(FAKE), i64(10), i64(11), 1, arr(FAKE), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_prune(arr(FAKE), i64(-1), i64(0), 1, arr(FAKE), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_prune(arr(None), i64(10), i64(3), 1, arr(FAKE), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_prune(arr(FAKE), i64(10), i64(3), 1, arr(None), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_prune(arr(FAKE), i64(10), i64(3), 0, arr(FAKE), None) == lp.LPSIFT_EINVAL
+    # describe_selected
+    ws = 0x100000
+    need = lib.lpsift_describe_workspace_size(ims, 1, ctypes.byref(P))
+    call = lambda sel, ns, wsb=need: lib.lpsift_describe_selected(
+        ims, 1, ks, ctypes.byref(P), sel, ns, ws, wsb, arr(FAKE), arr(FAKE), None)
+    assert call(arr(FAKE), i64(-1)) == lp.LPSIFT_EINVAL
+    assert call(arr(None), i64(5)) == lp.LPSIFT_EINVAL
+    assert call(None, i64(5)) == lp.LPSIFT_EINVAL
+    assert call(arr(FAKE), i64(5), need - 1) == lp.LPSIFT_ECAPACITY
+    # gather: 4-byte aligned patches
+    assert lib.lpsift_scorer_gather(ims, 1, ks, ctypes.byref(P), None, None, arr(FAKE + 1),
+                                    arr(FAKE), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_scorer_gather(ims, 1, ks, ctypes.byref(P), arr(FAKE), None, arr(FAKE),
+                                    arr(FAKE), None) == lp.LPSIFT_EINVAL
+    # training step
+    assert lib.lpsift_scorer_train_workspace_size(0) == 0
+    wsz = lib.lpsift_scorer_train_workspace_size(100)
+    assert wsz >= 2 * (20801 + 2) * 4                  # two partial-sum rows of 64 candidates
+    step = lambda b=100, t=1, lr=1e-3, wsb=wsz: lib.lpsift_scorer_train_step(
+        FAKE, FAKE, FAKE, FAKE, b, FAKE, FAKE, FAKE, t, lr, ws, wsb, None, None)
+    assert step(b=0) == lp.LPSIFT_EINVAL
+    assert step(t=0) == lp.LPSIFT_EINVAL
+    assert step(lr=0.0) == lp.LPSIFT_EINVAL
+    assert step(lr=math.nan) == lp.LPSIFT_EINVAL
+    assert step(wsb=wsz - 1) == lp.LPSIFT_ECAPACITY
