@@ -11,10 +11,12 @@ per-kernel device times from the library's timing facility (HIP events
 recorded around every launch on the stream it runs on) and from them a roofline
 object for the dominant kernel (the FP32 matrix-core contraction of the
 matcher); side fields for the reduced-precision matchers and for the 9-tile
-all-pairs workload (tuned work split, HIP-graph replay); and the FP64 oracle
-timed on a bounded sample on the host.
+all-pairs workload (tuned work split, HIP-graph replay) and for learned
+keypoint pruning against the plain path on 32 mixed-size pairs; and the FP64
+oracle timed on a bounded sample on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-tiles]
+                    [--no-learned]
 """
 import argparse
 import json
@@ -38,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tiles", action="store_true",
                     help="skip the 9-tile all-pairs side measurement")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-pruning side measurement (32 mixed-size pairs)")
+    ap.add_argument("--learned-pairs", type=int, default=32)
     ap.add_argument("--cpu-queries", type=int, default=12288,
                     help="reference descriptors in the oracle's timed match sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -200,6 +205,69 @@ def bench_tiles(args, dev):
     return res
 
 
+def bench_learned(args, dev, pairs):
+    """Learned pruning vs the plain path on mixed-size pairs (1024x768 ..
+    4000x3000): GPU pairs/s of both paths (detect .. match, inputs resident),
+    then host RANSAC on both results; the learned path falls back to the plain
+    path for a pair whose RANSAC keeps fewer than 12 inliers."""
+    import numpy as np
+    import torch
+    import paper_2405_08578_amd as lp
+    from paper_2405_08578_amd import learned as L
+
+    w, info = L.load_weights(L.DEFAULT_WEIGHTS, dev)
+    P = lp.Params([16, 32, 64, 128])
+    imgs = [[torch.from_numpy(p.A).to(dev), torch.from_numpy(p.B).to(dev)] for p in pairs]
+    mpix = sum(2 * p.A.size for p in pairs) / 1e6
+
+    def plain_step():
+        return [L.plain_gpu(im, P) for im in imgs]
+
+    def learned_step():
+        return [L.learned_gpu(im, P, w) for im in imgs]
+
+    steps = max(1, min(3, args.steps // 5))
+    out = {}
+    for name, fn in (("plain", plain_step), ("learned", learned_step)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = fn()
+        torch.cuda.synchronize()
+        out[name] = ((time.perf_counter() - t0) * 1000.0 / steps, res)
+    rows = []
+    t0 = time.perf_counter()
+    for k, p in enumerate(pairs):
+        pl = L.finish(out["plain"][1][k], seed=k, H_true=p.H)
+        le = L.finish(out["learned"][1][k], seed=k, H_true=p.H)
+        fb = le["inliers"] < 12
+        if fb:
+            le = pl
+        rows.append((pl["inliers"], le["inliers"], pl["gt_consistent"], le["gt_consistent"], fb,
+                     pl["matches"], le["matches"]))
+    t_host = (time.perf_counter() - t0) / (2 * len(pairs))
+    r = np.array(rows, dtype=np.float64)
+    ms_p, ms_l = out["plain"][0], out["learned"][0]
+    return {"workload": f"{len(pairs)} mixed-size pairs (widths 1024-4000, 4:3, blob texture, "
+                        f"random similarity, IoU 0.3-0.5), L 16/32/64/128; learned path keeps "
+                        f"ceil(0.3 n) keypoints per image by scorer logit",
+            "images": 2 * len(pairs), "megapixels": round(mpix, 1),
+            "plain_pairs_per_s": round(len(pairs) * 1000.0 / ms_p, 2),
+            "learned_pairs_per_s": round(len(pairs) * 1000.0 / ms_l, 2),
+            "speedup": round(ms_p / ms_l, 2),
+            "plain_ms_per_step": round(ms_p, 2), "learned_ms_per_step": round(ms_l, 2),
+            "ransac_inliers_plain": int(r[:, 0].sum()), "ransac_inliers_learned": int(r[:, 1].sum()),
+            "inlier_retention": round(r[:, 1].sum() / max(r[:, 0].sum(), 1), 4),
+            "gt_consistent_plain": int(r[:, 2].sum()), "gt_consistent_learned": int(r[:, 3].sum()),
+            "gt_match_retention": round(r[:, 3].sum() / max(r[:, 2].sum(), 1), 4),
+            "min_pair_gt_retention": round(float(np.min(r[:, 3] / np.maximum(r[:, 2], 1))), 4),
+            "fallbacks": int(r[:, 4].sum()),
+            "matches_plain": int(r[:, 5].sum()), "matches_learned": int(r[:, 6].sum()),
+            "host_ransac_ms_per_pair": round(1000.0 * t_host, 2),
+            "weights_sha256": info["sha256"][:16]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -207,6 +275,16 @@ def main():
               "(images and match pairs would shard across GPUs with no reduction)",
               file=sys.stderr)
         sys.exit(2)
+
+    # mixed-size pairs for the learned-pruning measurement: rendered by host
+    # processes started before this process touches the GPU
+    learned_job = pool = None
+    if not args.no_learned:
+        import multiprocessing as mp
+        import synth
+        pool = mp.get_context("spawn").Pool(16)
+        learned_job = pool.map_async(synth.make_mixed_pair,
+                                     synth.mixed_pair_specs(args.learned_pairs), chunksize=1)
 
     import numpy as np
     import torch
@@ -247,6 +325,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if learned_job is not None:
+        learned_job.wait()       # no host workers compete with the timed region
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -340,6 +420,12 @@ def main():
 
     if not args.no_tiles:
         out["all_pairs_tiles"] = bench_tiles(args, dev)
+    if learned_job is not None:
+        mixed = learned_job.get()
+        pool.close()
+        pool.join()
+        out["learned_pruning"] = bench_learned(args, dev, mixed)
+        del mixed
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(pair, Ls, args.cpu_queries)

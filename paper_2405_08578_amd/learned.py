@@ -1,0 +1,220 @@
+"""Learned keypoint pruning on top of the plain LP-SIFT path.
+
+Plain path of a pair:   detect -> describe every slot -> match -> RANSAC.
+Learned path of a pair: detect -> score every slot -> keep the best 30 % per
+image -> describe the kept slots -> match -> RANSAC; if RANSAC then keeps fewer
+than `min_inliers` inliers, the pair is redone on the plain path (fallback).
+
+Training labels come from the plain path itself: a keypoint is positive when
+it is an endpoint of a match that RANSAC keeps as an inlier.
+
+Every GPU step is a library call (lpsift_detect, lpsift_score, lpsift_prune,
+lpsift_describe[_selected], lpsift_match, lpsift_scorer_gather,
+lpsift_scorer_train_step); RANSAC is the library's host routine. This module
+is orchestration only: buffers, index bookkeeping on the host, the training
+loop and the weight file.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import (Params, ScorerTrainer, describe, describe_selected, detect, keep_count, match,
+               prune, ransac, score, scorer_gather, SCORER_PARAMS)
+
+WEIGHTS_VERSION = 1
+RANSAC_ITERS = 2000
+RANSAC_THRESH = 3.0
+
+
+def _host(kp) -> Dict[str, np.ndarray]:
+    return {k: v.cpu().numpy() for k, v in kp.items()}
+
+
+def ransac_pair(xyA: np.ndarray, xyB: np.ndarray, seed: int, n_iter: int = RANSAC_ITERS,
+                thresh: float = RANSAC_THRESH):
+    """Host RANSAC with seeded hypothesis draws; (H or None, inlier mask)."""
+    import synth
+    n = len(xyA)
+    if n < 4:
+        return None, np.zeros(n, bool)
+    samples = synth.ransac_samples(n, n_iter, np.random.default_rng(seed))
+    H, mask, _ = ransac(xyA, xyB, samples, thresh)
+    return H, mask
+
+
+def matched_points(kpA, kpB, m, selA=None, selB=None):
+    """Slots and coordinates of the accepted matches (host arrays)."""
+    qi = np.nonzero(m >= 0)[0]
+    sa = qi if selA is None else selA[qi]
+    sb = m[qi] if selB is None else selB[m[qi]]
+    xyA = np.stack([kpA["x"][sa], kpA["y"][sa]], axis=1).astype(np.float64)
+    xyB = np.stack([kpB["x"][sb], kpB["y"][sb]], axis=1).astype(np.float64)
+    return sa, sb, xyA, xyB
+
+
+def plain_gpu(imgs, P: Params, precision: int = 0):
+    """Plain GPU path of one pair up to the match list (no synchronisation)."""
+    kps = detect(imgs, P)
+    _, desc = describe(imgs, kps, P)
+    r = match([desc[0]], [desc[1]], precision=precision)[0]
+    return {"kps": kps, "match": r["match"]}
+
+
+def learned_gpu(imgs, P: Params, weights, num: int = 3, den: int = 10, precision: int = 0):
+    """Learned GPU path of one pair up to the match list (no synchronisation)."""
+    kps = detect(imgs, P)
+    sc = score(imgs, kps, P, weights)
+    sel = prune(sc, [keep_count(s.numel(), num, den) for s in sc])
+    _, desc = describe_selected(imgs, kps, P, sel)
+    r = match([desc[0]], [desc[1]], precision=precision)[0]
+    return {"kps": kps, "sel": sel, "match": r["match"]}
+
+
+def gt_consistent(xyA: np.ndarray, xyB: np.ndarray, H_true: np.ndarray,
+                  thresh: float = RANSAC_THRESH) -> int:
+    """Matches whose A point maps within `thresh` px of its B point under the
+    known homography of a synthetic pair."""
+    if len(xyA) == 0:
+        return 0
+    p = np.c_[xyA, np.ones(len(xyA))] @ np.asarray(H_true, np.float64).T
+    q = p[:, :2] / p[:, 2:3]
+    return int((np.linalg.norm(q - xyB, axis=1) < thresh).sum())
+
+
+def finish(res, seed: int, H_true: Optional[np.ndarray] = None):
+    """Host side of a pair: matched points, RANSAC, inlier slots (and the
+    ground-truth-consistent match count when the true homography is known)."""
+    kpA, kpB = _host(res["kps"][0]), _host(res["kps"][1])
+    m = res["match"].cpu().numpy()
+    selA = selB = None
+    if "sel" in res:
+        selA, selB = res["sel"][0].cpu().numpy(), res["sel"][1].cpu().numpy()
+    sa, sb, xyA, xyB = matched_points(kpA, kpB, m, selA, selB)
+    H, mask = ransac_pair(xyA, xyB, seed)
+    out = {"H": H, "matches": int(len(sa)), "inliers": int(mask.sum()),
+           "inlier_slots": (sa[mask], sb[mask]), "n_kp": (len(kpA["x"]), len(kpB["x"]))}
+    if H_true is not None:
+        out["gt_consistent"] = gt_consistent(xyA, xyB, H_true)
+    return out
+
+
+def run_pair(imgs, P: Params, weights=None, seed: int = 0, min_inliers: int = 12,
+             precision: int = 0, H_true: Optional[np.ndarray] = None):
+    """One pair end to end: the learned path with plain fallback when weights
+    are given, else the plain path."""
+    if weights is None:
+        out = finish(plain_gpu(imgs, P, precision), seed, H_true)
+        out["path"] = "plain"
+        return out
+    out = finish(learned_gpu(imgs, P, weights, precision=precision), seed, H_true)
+    out["path"] = "learned"
+    if out["inliers"] < min_inliers:
+        out = finish(plain_gpu(imgs, P, precision), seed, H_true)
+        out["path"] = "fallback"
+    return out
+
+
+# ----------------------------------------------------------------- training --
+
+def pair_records(imgs, P: Params, seed: int, neg_per_pos: int = 4):
+    """Training records of one pair: every plain-path RANSAC-inlier endpoint
+    (label 1) and neg_per_pos times as many other keypoints (label 0), drawn
+    with a seeded generator; returns (patches, extra, labels) on the device."""
+    import torch
+    res = plain_gpu(imgs, P)
+    fin = finish(res, seed)
+    rng = np.random.default_rng(seed + 1)
+    pats, exts, labs = [], [], []
+    for side in (0, 1):
+        n = fin["n_kp"][side]
+        pos = np.unique(fin["inlier_slots"][side])
+        lab = np.zeros(n, bool)
+        lab[pos] = True
+        negs = np.nonzero(~lab)[0]
+        k = min(len(negs), max(neg_per_pos * len(pos), 64))
+        neg = rng.choice(negs, k, replace=False) if k > 0 else negs[:0]
+        sel = np.concatenate([pos, neg]).astype(np.int32)
+        dev = imgs[side].device
+        pa, ex = scorer_gather([imgs[side]], [res["kps"][side]], P, [torch.from_numpy(sel).to(dev)])
+        pats.append(pa[0])
+        exts.append(ex[0])
+        labs.append(torch.from_numpy(np.r_[np.ones(len(pos)), np.zeros(len(neg))]
+                                     .astype(np.float32)).to(dev))
+    return torch.cat(pats), torch.cat(exts), torch.cat(labs), fin["inliers"]
+
+
+def train(patches, extra, labels, init, steps: int, batch: int = 8192, lr: float = 1e-3,
+          seed: int = 0, log=None, lr_final: float = 1.0):
+    """Adam on balanced class weights over shuffled minibatches, the step size
+    decaying from lr to lr * lr_final on a half cosine; returns the FP32
+    weights (device) and the loss history."""
+    import math
+    import torch
+    dev = patches.device
+    n = int(labels.numel())
+    pos = float(labels.sum().item())
+    w_pos = (n - pos) / max(pos, 1.0)
+    cweight = torch.where(labels > 0.5, torch.tensor(w_pos, device=dev),
+                          torch.tensor(1.0, device=dev)).float().contiguous()
+    tr = ScorerTrainer(torch.from_numpy(np.asarray(init, np.float32).copy()).to(dev), batch)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    losses = []
+    order = torch.randperm(n, generator=g)
+    at = 0
+    for s in range(steps):
+        if at + batch > n:
+            order = torch.randperm(n, generator=g)
+            at = 0
+        idx = order[at:at + batch].to(dev)
+        at += batch
+        frac = s / max(steps - 1, 1)
+        lr_s = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * frac)))
+        tr.step(patches[idx].contiguous(), extra[idx].contiguous(), labels[idx].contiguous(),
+                cweight[idx].contiguous(), lr_s)
+        if s % 500 == 0 or s == steps - 1:
+            losses.append((s, float(tr.loss.item())))
+            if log:
+                log(f"step {s} loss {losses[-1][1]:.4f}")
+    return tr.weights, losses
+
+
+# ------------------------------------------------------------- weight file --
+
+def save_weights(path: str, weights: np.ndarray, meta: Dict):
+    """<path>.bin: 20,801 little-endian float32 values; <path>.json: metadata
+    (version, parameter layout, feature spec, training config, sha256)."""
+    w = np.asarray(weights, dtype="<f4")
+    if w.size != SCORER_PARAMS:
+        raise ValueError("wrong parameter count")
+    raw = w.tobytes()
+    with open(path + ".bin", "wb") as f:
+        f.write(raw)
+    info = dict(meta)
+    info.update({"version": WEIGHTS_VERSION, "params": SCORER_PARAMS,
+                 "layout": "W1[64][258], b1[64], W2[64][64], b2[64], w3[64], b3[1] (float32 LE)",
+                 "features": "16x16 patch I(y+r-8, x+c-8)/255 at 16r+c (0 outside), "
+                             "normalised log2 L, contrast",
+                 "sha256": hashlib.sha256(raw).hexdigest()})
+    with open(path + ".json", "w") as f:
+        json.dump(info, f, indent=1, sort_keys=True)
+
+
+def load_weights(path: str, device=None):
+    """Weights as a float32 tensor on `device` (checked against the metadata)."""
+    import torch
+    with open(path + ".json") as f:
+        info = json.load(f)
+    raw = open(path + ".bin", "rb").read()
+    if info.get("version") != WEIGHTS_VERSION or hashlib.sha256(raw).hexdigest() != info["sha256"]:
+        raise ValueError(f"{path}: weight file does not match its metadata")
+    w = np.frombuffer(raw, dtype="<f4").astype(np.float32)
+    t = torch.from_numpy(w.copy())
+    return (t.to(device) if device is not None else t), info
+
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "scorer", "lpsift_scorer_v1")

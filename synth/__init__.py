@@ -304,10 +304,10 @@ def make_tiles(world_w: int = 7000, world_h: int = 4500, grid: int = 3,
     return TileSet([tiles[k] for k in order], [Hs[k] for k in order], order, seed)
 
 
-def make_mixed_pairs(n_pairs: int = 32, w_range=(1024, 4000), seed: Optional[int] = None,
-                     blob_density: float = 2000 / (2600 * 1600)) -> List[Pair]:
-    """Pairs of mixed sizes, height = round(0.75 width), generated like the
-    2600x1600 pair with the blob density scaled to the image area."""
+def mixed_pair_specs(n_pairs: int = 32, w_range=(1024, 4000), seed: Optional[int] = None,
+                     blob_density: float = 2000 / (2600 * 1600)) -> List[Tuple[int, int, int, int]]:
+    """(width, height, blobs, seed) of each mixed-size pair, height =
+    round(0.75 width), the blob density of the 2600x1600 pair."""
     seed = seed_for(4) if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
@@ -315,8 +315,20 @@ def make_mixed_pairs(n_pairs: int = 32, w_range=(1024, 4000), seed: Optional[int
         w = int(rng.integers(w_range[0], w_range[1] + 1))
         h = int(round(0.75 * w))
         nb = int(round(blob_density * w * h))
-        out.append(make_pair_random(w, h, nb, seed=int(rng.integers(1 << 62))))
+        out.append((w, h, nb, int(rng.integers(1 << 62))))
     return out
+
+
+def make_mixed_pair(spec: Tuple[int, int, int, int]) -> Pair:
+    w, h, nb, s = spec
+    return make_pair_random(w, h, nb, seed=s)
+
+
+def make_mixed_pairs(n_pairs: int = 32, w_range=(1024, 4000), seed: Optional[int] = None,
+                     blob_density: float = 2000 / (2600 * 1600)) -> List[Pair]:
+    """Pairs of mixed sizes, generated like the 2600x1600 pair with the blob
+    density scaled to the image area (see mixed_pair_specs)."""
+    return [make_mixed_pair(s) for s in mixed_pair_specs(n_pairs, w_range, seed, blob_density)]
 
 
 # --------------------------------------------------------------------------
