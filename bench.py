@@ -213,9 +213,11 @@ def bench_tiles(args, dev):
 
 def bench_learned(args, dev, pairs):
     """Learned pruning vs the plain path on mixed-size pairs (1024x768 ..
-    4000x3000): GPU pairs/s of both paths (detect .. match, inputs resident),
-    then host RANSAC on both results; the learned path falls back to the plain
-    path for a pair whose RANSAC keeps fewer than 12 inliers."""
+    4000x3000): GPU pairs/s of both paths over all pairs at once (every image
+    in the same detect/score/prune/describe calls, all pairs in one match
+    call; inputs resident), then host RANSAC on both results; the learned path
+    falls back to the plain path for a pair whose RANSAC keeps fewer than 12
+    inliers."""
     import numpy as np
     import torch
     import paper_2405_08578_amd as lp
@@ -227,10 +229,10 @@ def bench_learned(args, dev, pairs):
     mpix = sum(2 * p.A.size for p in pairs) / 1e6
 
     def plain_step():
-        return [L.plain_gpu(im, P) for im in imgs]
+        return L.plain_gpu_batch(imgs, P)
 
     def learned_step():
-        return [L.learned_gpu(im, P, w) for im in imgs]
+        return L.learned_gpu_batch(imgs, P, w)
 
     steps = max(1, min(3, args.steps // 5))
     out = {}

@@ -223,8 +223,8 @@ int lpsift_score(const lpsift_image* imgs, int32_t n_images, const lpsift_keypoi
 /* Top-k prune: for each image i, the k[i] slots with the largest scores
  * scores[i][0 .. n[i]) (larger score first, lower slot on ties; NaN ranks
  * lowest), written to sel[i][0 .. k[i]) in ascending slot order. Host arrays
- * n, k, and of device pointers scores, sel. Errors: EINVAL (k > n, negative
- * counts, null pointers), EHIP. */
+ * n, k, and of device pointers scores (16-byte aligned), sel. Errors: EINVAL
+ * (k > n, negative counts, null or misaligned pointers), EHIP. */
 int lpsift_prune(const float* const* scores, const int64_t* n, const int64_t* k,
                  int32_t n_images, int32_t* const* sel, void* stream);
 

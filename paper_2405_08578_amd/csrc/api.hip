@@ -237,6 +237,7 @@ int lpsift_prune(const float* const* scores, const int64_t* n, const int64_t* k,
     for (int i = 0; i < n_images; ++i) {
         if (n[i] < 0 || n[i] > INT32_MAX || k[i] < 0 || k[i] > n[i]) return LPSIFT_EINVAL;
         if (n[i] > 0 && !scores[i]) return LPSIFT_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(scores[i]) & 15u) != 0) return LPSIFT_EINVAL;
         if (k[i] > 0 && !sel[i]) return LPSIFT_EINVAL;
     }
     for (int b0 = 0; b0 < n_images; b0 += kMaxBatch) {

@@ -32,6 +32,9 @@ constexpr float kTwoPiInv = 0.15915494309189535f;  // 1 / (2 pi)
 
 // Images per launch (keeps the by-value kernel arguments small).
 constexpr int kDescBatch = kMaxBatch;
+// Gradient-field bytes per launch group: half of MI355X's 256 MB last-level
+// (Infinity) cache, where the describe kernel's repeated field reads then hit.
+constexpr size_t kFieldGroupBytes = 128u << 20;
 
 // ---------------------------------------------------------------- tables --
 
@@ -427,8 +430,18 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
     if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
     size_t foff = field_offset(g);
-    for (int b0 = 0; b0 < n; b0 += kDescBatch) {
-        const int nb = (n - b0 < kDescBatch) ? n - b0 : kDescBatch;
+    for (int b0 = 0, nb = 0; b0 < n; b0 += nb) {
+        // images per launch pair (field + describe): at most kDescBatch, and
+        // gradient fields of at most kFieldGroupBytes together so that they
+        // stay in the last-level cache while the describe kernel reads them
+        size_t group = 0;
+        nb = 0;
+        while (b0 + nb < n && nb < kDescBatch) {
+            const size_t fb = (size_t)imgs[b0 + nb].height * (size_t)imgs[b0 + nb].width * sizeof(float2);
+            if (nb > 0 && group + fb > kFieldGroupBytes) break;
+            group += fb;
+            ++nb;
+        }
         FieldArgs fa{};
         DescArgs da{};
         fa.n_images = nb;

@@ -226,6 +226,26 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* total, uint32_t* sh)
     return before + x - v;
 }
 
+constexpr int kPer = 8;                          // scores per thread per tile
+constexpr int kPruneTile = kPruneThreads * kPer;
+
+// Keys of the 8 scores [i, i + 8) (i a multiple of 8; the scores are 16-byte
+// aligned); entries at or beyond n get key 0 and valid = false.
+__device__ inline void load_keys(const float* __restrict__ s, int64_t n, int64_t i,
+                                 uint32_t key[kPer])
+{
+    if (i + kPer <= n) {
+        const float4 a = *reinterpret_cast<const float4*>(s + i);
+        const float4 b = *reinterpret_cast<const float4*>(s + i + 4);
+        key[0] = score_key(a.x); key[1] = score_key(a.y); key[2] = score_key(a.z);
+        key[3] = score_key(a.w); key[4] = score_key(b.x); key[5] = score_key(b.y);
+        key[6] = score_key(b.z); key[7] = score_key(b.w);
+    } else {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) key[e] = (i + e < n) ? score_key(s[i + e]) : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kPruneThreads) void prune_kernel(PruneArgs a)
 {
     __shared__ uint32_t hist[256];
@@ -239,15 +259,21 @@ __global__ __launch_bounds__(kPruneThreads) void prune_kernel(PruneArgs a)
         for (int64_t i = threadIdx.x; i < n; i += kPruneThreads) P.sel[i] = (int32_t)i;
         return;
     }
-    // radix select of the k-th largest key, 8 bits at a time from the top
+    // radix select of the k-th largest key, 8 bits at a time from the top;
+    // thread t reads the run [tile + 8 t, tile + 8 t + 8) of every tile
     uint32_t prefix = 0u, mask = 0u;
     uint32_t need = (uint32_t)k;       // rank still to find among keys with this prefix
     for (int shift = 24; shift >= 0; shift -= 8) {
         for (int b = threadIdx.x; b < 256; b += kPruneThreads) hist[b] = 0u;
         __syncthreads();
-        for (int64_t i = threadIdx.x; i < n; i += kPruneThreads) {
-            const uint32_t key = score_key(P.score[i]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        for (int64_t i0 = 0; i0 < n; i0 += kPruneTile) {
+            const int64_t i = i0 + (int64_t)kPer * threadIdx.x;
+            uint32_t key[kPer];
+            load_keys(P.score, n, i, key);
+#pragma unroll
+            for (int e = 0; e < kPer; ++e)
+                if (i + e < n && (key[e] & mask) == prefix)
+                    atomicAdd(&hist[(key[e] >> shift) & 255u], 1u);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -270,17 +296,31 @@ __global__ __launch_bounds__(kPruneThreads) void prune_kernel(PruneArgs a)
     // (the lowest slots) complete the k
     const uint32_t T = prefix;
     uint32_t out_base = 0u, eq_base = 0u;
-    for (int64_t i0 = 0; i0 < n; i0 += kPruneThreads) {
-        const int64_t i = i0 + threadIdx.x;
-        uint32_t key = 0u;
-        if (i < n) key = score_key(P.score[i]);
-        const uint32_t is_eq = (i < n && key == T) ? 1u : 0u;
+    for (int64_t i0 = 0; i0 < n; i0 += kPruneTile) {
+        const int64_t i = i0 + (int64_t)kPer * threadIdx.x;
+        uint32_t key[kPer];
+        load_keys(P.score, n, i, key);
+        uint32_t n_eq = 0u;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) n_eq += (i + e < n && key[e] == T) ? 1u : 0u;
         uint32_t eq_tot;
-        const uint32_t eq_rank = eq_base + block_scan(is_eq, &eq_tot, sh);
-        const uint32_t keep = (i < n && (key > T || (is_eq && eq_rank < need))) ? 1u : 0u;
+        uint32_t eq_rank = eq_base + block_scan(n_eq, &eq_tot, sh);
+        uint32_t keep_mask = 0u, n_keep = 0u;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            bool keep = false;
+            if (i + e < n) {
+                if (key[e] > T) keep = true;
+                else if (key[e] == T) keep = (eq_rank++ < need);
+            }
+            keep_mask |= keep ? (1u << e) : 0u;
+            n_keep += keep ? 1u : 0u;
+        }
         uint32_t keep_tot;
-        const uint32_t pos = out_base + block_scan(keep, &keep_tot, sh);
-        if (keep) P.sel[pos] = (int32_t)i;
+        uint32_t pos = out_base + block_scan(n_keep, &keep_tot, sh);
+#pragma unroll
+        for (int e = 0; e < kPer; ++e)
+            if (keep_mask & (1u << e)) P.sel[pos++] = (int32_t)(i + e);
         out_base += keep_tot;
         eq_base += eq_tot;
     }

@@ -75,6 +75,30 @@ def learned_gpu(imgs, P: Params, weights, num: int = 3, den: int = 10, precision
     return {"kps": kps, "sel": sel, "match": r["match"]}
 
 
+def plain_gpu_batch(pairs, P: Params, precision: int = 0):
+    """Plain GPU path of many pairs [[A, B], ...] at once: every image in the
+    same detect and describe calls, all pairs in one match call (the library
+    batches up to 16 images / pairs per launch)."""
+    imgs = [t for pr in pairs for t in pr]
+    kps = detect(imgs, P)
+    _, desc = describe(imgs, kps, P)
+    r = match(desc[0::2], desc[1::2], precision=precision)
+    return [{"kps": kps[2 * i:2 * i + 2], "match": r[i]["match"]} for i in range(len(pairs))]
+
+
+def learned_gpu_batch(pairs, P: Params, weights, num: int = 3, den: int = 10,
+                      precision: int = 0):
+    """Learned GPU path of many pairs at once (see plain_gpu_batch)."""
+    imgs = [t for pr in pairs for t in pr]
+    kps = detect(imgs, P)
+    sc = score(imgs, kps, P, weights)
+    sel = prune(sc, [keep_count(s.numel(), num, den) for s in sc])
+    _, desc = describe_selected(imgs, kps, P, sel)
+    r = match(desc[0::2], desc[1::2], precision=precision)
+    return [{"kps": kps[2 * i:2 * i + 2], "sel": sel[2 * i:2 * i + 2], "match": r[i]["match"]}
+            for i in range(len(pairs))]
+
+
 def gt_consistent(xyA: np.ndarray, xyB: np.ndarray, H_true: np.ndarray,
                   thresh: float = RANSAC_THRESH) -> int:
     """Matches whose A point maps within `thresh` px of its B point under the

@@ -228,6 +228,7 @@ def test_scorer_entry_validation(lib):
     assert lib.lpsift_prune(arr(None), i64(10), i64(3), 1, arr(FAKE), None) == lp.LPSIFT_EINVAL
     assert lib.lpsift_prune(arr(FAKE), i64(10), i64(3), 1, arr(None), None) == lp.LPSIFT_EINVAL
     assert lib.lpsift_prune(arr(FAKE), i64(10), i64(3), 0, arr(FAKE), None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_prune(arr(FAKE + 4), i64(10), i64(3), 1, arr(FAKE), None) == lp.LPSIFT_EINVAL
     # describe_selected
     ws = 0x100000
     need = lib.lpsift_describe_workspace_size(ims, 1, ctypes.byref(P))

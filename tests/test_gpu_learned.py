@@ -58,3 +58,20 @@ def test_fallback_when_pruning_fails(gpu):
     le = L.run_pair(imgs, P, zero, seed=3, min_inliers=raw["inliers"] + 1)
     assert le["path"] == "fallback"
     assert le["inliers"] == pl["inliers"] and le["matches"] == pl["matches"]
+
+
+def test_batched_paths_equal_per_pair(gpu):
+    pairs = [synth.config_pair(0), synth.make_mixed_pair((1100, 825, 430, 5))]
+    P = lp.Params([16, 32, 64])
+    imgs = [[to_dev(p.A, gpu), to_dev(p.B, gpu)] for p in pairs]
+    w = load(gpu)
+    say("batched plain / learned paths")
+    bp = L.plain_gpu_batch(imgs, P)
+    bl = L.learned_gpu_batch(imgs, P, w)
+    for k, im in enumerate(imgs):
+        sp = L.plain_gpu(im, P)
+        sl = L.learned_gpu(im, P, w)
+        assert np.array_equal(bp[k]["match"].cpu().numpy(), sp["match"].cpu().numpy())
+        assert np.array_equal(bl[k]["match"].cpu().numpy(), sl["match"].cpu().numpy())
+        for a, b in zip(bl[k]["sel"], sl["sel"]):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
