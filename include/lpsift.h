@@ -68,8 +68,10 @@ enum lpsift_kernel {
 
 /* Method parameters (Sec. 2.2-2.3).
  *  n_scales  number of window sizes, 1..LPSIFT_MAX_SCALES
- *  L         window sides, strictly ascending, L[0] >= 4. On the GPU each L must
- *            divide the next and the largest must be <= 128 (nested windows).
+ *  L         window sides, strictly ascending, 4 <= L <= 65536. Any set works;
+ *            nested sets (each L divides the next) with the largest <= 128 use
+ *            the tiled detect kernel, other sets (e.g. {32, 40}, {256, 512})
+ *            one workgroup per window.
  *  d         subregions per side of the descriptor square; only 4 is built.
  *  beta0     Eq. 3-4 size factor; <= 0 selects the largest admissible value
  *            (1/d) sqrt(Lmin/Lmax), for which w = d w_s <= L at every scale. */
@@ -110,7 +112,8 @@ typedef struct lpsift_keypoints {
 } lpsift_keypoints;
 
 /* Matching parameters (Sec. 2.4, Eq. 6).
- *  ratio       a query is kept when d1 < ratio * d2 (compared in double)
+ *  ratio       a query is kept when d1 < ratio * d2 (compared in double);
+ *              +inf disables the ratio test (the absolute threshold alone)
  *  abs_thresh  ... and d1 < abs_thresh (the Delta_s of Eq. 6; +inf disables it)
  *  precision   contraction used to select candidates (d1 and d2 are always
  *              direct FP32 distances of the selected candidates):
@@ -156,8 +159,7 @@ int64_t lpsift_num_keypoints(int32_t height, int32_t width, const lpsift_params*
  *  out     host array of n_images keypoint buffers, each with capacity >=
  *          lpsift_num_keypoints(image); every slot is written.
  * Errors: EINVAL (null pointer, n_images < 1, empty image, pitch < width, bad
- * params), ECAPACITY (capacity too small), EUNSUPPORTED (L set not nested or
- * Lmax > 128), EHIP. */
+ * params), ECAPACITY (capacity too small), EUNSUPPORTED (d != 4), EHIP. */
 int lpsift_detect(const lpsift_image* imgs, int32_t n_images, const lpsift_params* params,
                   const lpsift_keypoints* out, void* stream);
 

@@ -241,7 +241,9 @@ void oracle_describe(const uint8_t* img, int32_t h, int32_t w, int64_t pitch,
 /* Nearest-neighbour matching with the distance of Eq. 6 and a ratio test.
  * For every reference row i: j1[i] = argmin_j |A_i - B_j| (lowest j on ties),
  * d1 = that distance, d2 = the second smallest distance over j != j1 (+inf when
- * nB < 2), match[i] = j1 if d1 < ratio * d2 and d1 < abs_thresh, else -1. */
+ * nB < 2), match[i] = j1 if d1 < ratio * d2 and d1 < abs_thresh, else -1.
+ * ratio = +inf leaves the absolute threshold of Eq. 6 alone (no ratio test,
+ * so equal d1 and d2 are not rejected). */
 void oracle_match(const double* A, int64_t nA, const double* B, int64_t nB, int32_t dim,
                   double ratio, double abs_thresh,
                   int32_t* j1, double* d1, double* d2, int32_t* match)
@@ -265,7 +267,8 @@ void oracle_match(const double* A, int64_t nA, const double* B, int64_t nB, int3
         j1[i] = (int32_t)jb;
         d1[i] = e1;
         d2[i] = e2;
-        match[i] = (jb >= 0 && e1 < ratio * e2 && e1 < abs_thresh) ? (int32_t)jb : -1;
+        const int ratio_ok = isinf(ratio) || e1 < ratio * e2;
+        match[i] = (jb >= 0 && ratio_ok && e1 < abs_thresh) ? (int32_t)jb : -1;
     }
 }
 

@@ -21,11 +21,7 @@ int make_geometry(const lpsift_params* p, Geometry* g)
         if (s > 0 && p->L[s] <= p->L[s - 1]) return LPSIFT_EINVAL;
     }
     if (p->d != 4) return LPSIFT_EUNSUPPORTED;
-    // nested windows, largest at most 128: what the tile kernel is built for
-    for (int s = 1; s < p->n_scales; ++s)
-        if (p->L[s] % p->L[s - 1] != 0) return LPSIFT_EUNSUPPORTED;
     const int Lmin = p->L[0], Lmax = p->L[p->n_scales - 1];
-    if (Lmax > 128) return LPSIFT_EUNSUPPORTED;
 
     // Eq. 3-4: beta = beta0 (L/Lmax)^(-1/2), w_s = beta L; default beta0 is the
     // largest value with w = d w_s <= L at every scale
@@ -313,7 +309,7 @@ int lpsift_scorer_train_step(const uint8_t* patches, const float* extra, const f
 static int check_match_params(const lpsift_match_params* mp)
 {
     if (!mp) return LPSIFT_EINVAL;
-    if (!(mp->ratio > 0.0) || !std::isfinite(mp->ratio)) return LPSIFT_EINVAL;
+    if (!(mp->ratio > 0.0)) return LPSIFT_EINVAL;      // +inf: no ratio test (Eq. 6 alone)
     if (std::isnan(mp->abs_thresh) || !(mp->abs_thresh > 0.0f)) return LPSIFT_EINVAL;
     if (mp->b_chunks < 0 || mp->b_chunks > 16) return LPSIFT_EINVAL;
     if (mp->precision < 0 || mp->precision > 3) return LPSIFT_EINVAL;

@@ -1,6 +1,7 @@
 // Multiscale window extrema (Sec. 2.2, Eq. 2) with the Eq. 1 ramp folded into
 // an exact integer key.
 //
+// Nested window sets with windows of at most 128 px (the fast path):
 // One workgroup owns a T x T tile of one image, T a multiple of the largest
 // window side (about 128 px; the largest window is at most 128). The tile is
 // staged once in LDS with coalesced 4-byte loads; every pixel becomes the key
@@ -182,11 +183,150 @@ __global__ __launch_bounds__(kThreads) void detect_kernel(DetectArgs args)
     }
 }
 
+// ---- any window set: one workgroup per window ----
+//
+// For L sets that are not nested, or with windows above 128 px, each window
+// is reduced on its own: key (value << 32 | y W + x) orders pixels exactly as
+// Eq. 1 does over the whole image (max: largest value, then largest raster
+// index; min: smallest value, then smallest index), and the window's integer
+// pixel sum gives the contrast, divided in double and rounded once to FP32.
+
+struct WinArgs {
+    int32_t n_images;
+    int32_t n_scales;
+    int32_t L[LPSIFT_MAX_SCALES];
+    int64_t first[kMaxBatch][LPSIFT_MAX_SCALES];   // first workgroup of (image, scale)
+    DetectImg img[kMaxBatch];
+};
+
+__device__ inline uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+__device__ inline uint64_t min_u64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+__global__ __launch_bounds__(kThreads) void detect_window_kernel(WinArgs a)
+{
+    __shared__ uint64_t smax[kThreads / 64], smin[kThreads / 64];
+    __shared__ uint32_t ssum[kThreads / 64];
+    // (image, scale, window) of this workgroup
+    const int64_t wg = blockIdx.x;
+    int im = 0, s = 0;
+    for (int i = 0; i < a.n_images; ++i)
+        for (int t = 0; t < a.n_scales; ++t)
+            if (wg >= a.first[i][t]) {
+                im = i;
+                s = t;
+            }
+    const DetectImg& I = a.img[im];
+    const int L = a.L[s];
+    const int64_t nbx = (I.w + L - 1) / L;
+    const int64_t win = wg - a.first[im][s];
+    const int by = (int)(win / nbx), bx = (int)(win - (int64_t)by * nbx);
+    const int x0 = bx * L, y0 = by * L;
+    const int ww = min(L, I.w - x0), wh = min(L, I.h - y0);
+    const int64_t npx = (int64_t)ww * wh;
+
+    uint64_t kmax = 0ull, kmin = ~0ull;
+    uint32_t sum = 0u;
+    for (int64_t p = threadIdx.x; p < npx; p += kThreads) {
+        const int r = (int)(p / ww), c = (int)(p - (int64_t)r * ww);
+        const int y = y0 + r, x = x0 + c;
+        const uint32_t v = I.data[(int64_t)y * I.pitch + x];
+        const uint64_t key = ((uint64_t)v << 32) | (uint32_t)(y * I.w + x);
+        kmax = max_u64(kmax, key);
+        kmin = min_u64(kmin, key);
+        sum += v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        kmax = max_u64(kmax, (uint64_t)__shfl_xor((long long)kmax, off));
+        kmin = min_u64(kmin, (uint64_t)__shfl_xor((long long)kmin, off));
+        sum += (uint32_t)__shfl_xor((int)sum, off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        smax[wave] = kmax;
+        smin[wave] = kmin;
+        ssum[wave] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kThreads / 64; ++k) {
+            kmax = max_u64(kmax, smax[k]);
+            kmin = min_u64(kmin, smin[k]);
+            sum += ssum[k];
+        }
+        const int64_t slot = I.base[s] + 2 * win;
+        const uint64_t keys[2] = {kmax, kmin};
+        for (int t = 0; t < 2; ++t) {
+            const uint32_t v = (uint32_t)(keys[t] >> 32);
+            const uint32_t idx = (uint32_t)keys[t];
+            I.x[slot + t] = (int32_t)(idx % (uint32_t)I.w);
+            I.y[slot + t] = (int32_t)(idx / (uint32_t)I.w);
+            I.scale[slot + t] = (uint8_t)s;
+            I.type[slot + t] = t == 0 ? (int8_t)1 : (int8_t)-1;
+            I.value[slot + t] = (uint8_t)v;
+            const int64_t num = (int64_t)v * npx - (int64_t)sum;
+            I.contrast[slot + t] =
+                (float)((double)(num < 0 ? -num : num) / (255.0 * (double)npx));
+        }
+    }
+}
+
+bool nested_small(const Geometry& g)
+{
+    for (int s = 1; s < g.n_scales; ++s)
+        if (g.L[s] % g.L[s - 1] != 0) return false;
+    return g.L[g.n_scales - 1] <= 128;
+}
+
+int launch_window_detect(const lpsift_image* imgs, int n, const Geometry& g,
+                         const lpsift_keypoints* out, hipStream_t stream)
+{
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = (n - b0 < kMaxBatch) ? n - b0 : kMaxBatch;
+        WinArgs a{};
+        a.n_images = nb;
+        a.n_scales = g.n_scales;
+        for (int s = 0; s < g.n_scales; ++s) a.L[s] = g.L[s];
+        int64_t wgs = 0;
+        for (int i = 0; i < nb; ++i) {
+            const lpsift_image& im = imgs[b0 + i];
+            const lpsift_keypoints& kp = out[b0 + i];
+            DetectImg& d = a.img[i];
+            d.data = im.data;
+            d.pitch = im.pitch;
+            d.h = im.height;
+            d.w = im.width;
+            d.x = kp.x;
+            d.y = kp.y;
+            d.scale = kp.scale;
+            d.type = kp.type;
+            d.value = kp.value;
+            d.contrast = kp.contrast;
+            int64_t base = 0;
+            for (int s = 0; s < g.n_scales; ++s) {
+                const int64_t nw = n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
+                d.base[s] = base;
+                base += 2 * nw;
+                a.first[i][s] = wgs;
+                wgs += nw;
+            }
+        }
+        if (wgs > 0x7FFFFFFF) return LPSIFT_EINVAL;
+        {
+            TimedScope ts(LPSIFT_KERNEL_DETECT, stream);
+            hipLaunchKernelGGL(detect_window_kernel, dim3((unsigned)wgs), dim3(kThreads), 0, stream,
+                               a);
+        }
+        if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+    }
+    return LPSIFT_OK;
+}
+
 }  // namespace
 
 int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,
                   const lpsift_keypoints* out, hipStream_t stream)
 {
+    if (!nested_small(g)) return launch_window_detect(imgs, n, g, out, stream);
     const int Lmax = g.L[g.n_scales - 1];
     const int T = Lmax * (Lmax < 128 ? 128 / Lmax : 1);   // ~128 px per tile side
     DetectArgs a{};

@@ -271,7 +271,9 @@ __device__ inline void write_result(int64_t q, float e1, int j1, float e2, doubl
                                     float abs_thresh, int32_t* match, float* d1out, float* d2out)
 {
     const float dd1 = sqrtf(e1), dd2 = sqrtf(e2);
-    const bool keep = j1 >= 0 && (double)dd1 < ratio * (double)dd2 && dd1 < abs_thresh;
+    // ratio = +inf: the absolute threshold of Eq. 6 alone
+    const bool ratio_ok = __builtin_isinf(ratio) || (double)dd1 < ratio * (double)dd2;
+    const bool keep = j1 >= 0 && ratio_ok && dd1 < abs_thresh;
     match[q] = keep ? j1 : -1;
     d1out[q] = dd1;
     d2out[q] = dd2;

@@ -93,10 +93,11 @@ def test_detect_validation(lib):
     assert detect(lib, bad, [image()], [kps(10**6)]) == lp.LPSIFT_EINVAL
     small = lp.Params([2, 16]).c()                      # L below 4
     assert detect(lib, small, [image()], [kps(10**6)]) == lp.LPSIFT_EINVAL
-    nonnested = lp.Params([32, 40]).c()                 # valid method, not on the GPU
-    assert detect(lib, nonnested, [image()], [kps(10**6)]) == lp.LPSIFT_EUNSUPPORTED
-    big = lp.Params([256, 512]).c()
-    assert detect(lib, big, [image()], [kps(10**6)]) == lp.LPSIFT_EUNSUPPORTED
+    huge = lp.Params([16, 70000]).c()                   # L above 65536
+    assert detect(lib, huge, [image()], [kps(10**6)]) == lp.LPSIFT_EINVAL
+    nonnested = lp.Params([32, 40]).c()                 # any set is valid: capacity checked
+    nk = lp.num_keypoints(64, 64, lp.Params([32, 40]))
+    assert detect(lib, nonnested, [image()], [kps(nk - 1)]) == lp.LPSIFT_ECAPACITY
     d8 = lp.Params([16, 32], d=8).c()
     assert detect(lib, d8, [image()], [kps(10**6)]) == lp.LPSIFT_EUNSUPPORTED
     zero = lp.lpsift_params()
@@ -146,6 +147,7 @@ def test_match_validation_and_workspace(lib):
     assert call(mp, dA=FAKE + 4) == lp.LPSIFT_EINVAL         # not 16-byte aligned
     assert call(mp, ws=0x100000 + 8) == lp.LPSIFT_EINVAL
     for bad in (lp.match_params(ratio=0.0), lp.match_params(ratio=math.nan),
+                lp.match_params(ratio=-math.inf),
                 lp.match_params(abs_thresh=math.nan), lp.match_params(abs_thresh=-1.0),
                 lp.match_params(b_chunks=17), lp.match_params(precision=4)):
         assert call(bad) == lp.LPSIFT_EINVAL

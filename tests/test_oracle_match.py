@@ -76,3 +76,22 @@ def test_degenerate_sizes():
     assert list(m["j1"]) == [-1, -1] and list(m["match"]) == [-1, -1]
     m = oracle.match(np.zeros((0, 2)), A)
     assert len(m["j1"]) == 0
+
+
+def test_abs_threshold_only_brute_force():
+    # ratio = +inf: Eq. 6's absolute threshold alone decides (no ratio test);
+    # duplicated registered rows (d1 = d2) are then kept when d1 < threshold
+    rng = np.random.default_rng(12)
+    B = rng.normal(size=(40, 16))
+    B[7] = B[3]
+    A = np.vstack([B[3] + 1e-3, rng.normal(size=(25, 16))])
+    tau = 4.0
+    o = oracle.match(A, B, ratio=math.inf, abs_thresh=tau)
+    D = cdist(A, B)
+    d1 = D.min(axis=1)
+    j1 = D.argmin(axis=1)
+    expect = np.where(d1 < tau, j1, -1)
+    assert np.array_equal(o["match"], expect)
+    assert o["match"][0] == 3 and o["d1"][0] == o["d2"][0]
+    # with the ratio test the same duplicate is rejected
+    assert oracle.match(A, B, ratio=0.8, abs_thresh=tau)["match"][0] == -1
