@@ -78,14 +78,39 @@ def reprojection_error(H: np.ndarray, pa: np.ndarray, pb: np.ndarray):
     return np.where(np.abs(w) > 1e-12, e, np.inf)
 
 
+def samples_from_uniforms(u: np.ndarray, n: int) -> np.ndarray:
+    """Hypothesis indices from uniform draws u [n_iter, 4, tries] in [0, 1)
+    when the number of matches n is only known at run time: slot s takes the
+    first try t whose floor(u n) differs from the indices of slots < s; a
+    hypothesis with a slot that finds none is -1 (skipped)."""
+    u = np.asarray(u, np.float64)
+    out = np.full((u.shape[0], 4), -1, np.int64)
+    if n < 4:
+        return out
+    for it in range(u.shape[0]):
+        got = []
+        for s in range(4):
+            for t in range(u.shape[2]):
+                i = min(int(np.floor(u[it, s, t] * n)), n - 1)
+                if i not in got:
+                    got.append(i)
+                    break
+            else:
+                break
+        if len(got) == 4:
+            out[it] = got
+    return out
+
+
 def ransac(pa: np.ndarray, pb: np.ndarray, samples: np.ndarray, thresh: float = 3.0):
-    """Returns (H or None, inlier mask, best hypothesis index)."""
+    """Returns (H or None, inlier mask, best hypothesis index). Rows of
+    samples holding -1 are skipped."""
     pa = np.asarray(pa, np.float64)
     pb = np.asarray(pb, np.float64)
     n = len(pa)
     best, best_cnt = -1, -1
     for it, idx in enumerate(np.asarray(samples)):
-        if n < 4 or degenerate(pa[idx]) or degenerate(pb[idx]):
+        if n < 4 or np.any(idx < 0) or degenerate(pa[idx]) or degenerate(pb[idx]):
             continue
         H = dlt(pa[idx], pb[idx])
         cnt = int((reprojection_error(H, pa, pb) < thresh).sum())

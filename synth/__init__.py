@@ -372,3 +372,10 @@ def scorer_init(rng: np.random.Generator, n_in: int = 258, n_hid: int = 64) -> n
             lim = math.sqrt(6.0 / fan_in)
             parts.append(rng.uniform(-lim, lim, int(np.prod(shape))))
     return np.concatenate(parts)
+
+
+def ransac_uniforms(n_iter: int, rng: np.random.Generator, tries: int = 8) -> np.ndarray:
+    """[n_iter, 4, tries] uniform draws in [0, 1) from which RANSAC hypotheses
+    are formed once the number of matches is known (the method's random
+    draws, passed in as inputs)."""
+    return rng.random((n_iter, 4, tries))

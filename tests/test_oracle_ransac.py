@@ -73,3 +73,41 @@ def test_degenerate_samples_are_skipped():
 def test_too_few_points():
     G, mask, best = R.ransac(np.zeros((3, 2)), np.zeros((3, 2)), np.zeros((5, 4), np.int32), 3.0)
     assert G is None and len(mask) == 3
+
+
+def test_samples_from_uniforms():
+    rng = np.random.default_rng(4)
+    u = rng.random((500, 4, 8))
+    for n in (4, 5, 9, 1000):
+        S = R.samples_from_uniforms(u, n)
+        ok = S[:, 0] >= 0
+        assert ok.mean() > (0.5 if n < 9 else 0.99)
+        v = S[ok]
+        assert np.all((v >= 0) & (v < n))
+        assert all(len(set(r)) == 4 for r in v.tolist())
+    # without collisions every slot is its first draw, floor(u n)
+    n = 10 ** 6
+    S = R.samples_from_uniforms(u, n)
+    assert np.array_equal(S, np.floor(u[:, :, 0] * n).astype(np.int64))
+    # hand-built collisions: slot 1 repeats slot 0 twice, then takes try 2
+    v = np.zeros((1, 4, 8))
+    v[0, :, 0] = [0.10, 0.11, 0.5, 0.9]
+    v[0, 1, 1] = 0.105
+    v[0, 1, 2] = 0.7
+    assert R.samples_from_uniforms(v, 10).tolist() == [[1, 7, 5, 9]]
+    assert np.all(R.samples_from_uniforms(u, 3) == -1)
+    # a slot with no distinct try leaves the hypothesis out
+    w = np.full((1, 4, 8), 0.25)
+    assert R.samples_from_uniforms(w, 10).tolist() == [[-1, -1, -1, -1]]
+
+
+def test_ransac_skips_invalid_rows():
+    rng = np.random.default_rng(5)
+    H = np.array([[1.02, 0.03, 5.0], [-0.02, 0.98, -3.0], [1e-5, 0, 1.0]])
+    pa = rng.uniform(0, 500, (60, 2))
+    q = np.c_[pa, np.ones(60)] @ H.T
+    pb = q[:, :2] / q[:, 2:]
+    samples = np.array([[-1, -1, -1, -1], [0, 1, 2, 3]])
+    Hr, mask, best = R.ransac(pa, pb, samples)
+    assert best == 1 and mask.all()
+    assert np.allclose(Hr, H / H[2, 2], atol=1e-9)
