@@ -56,7 +56,8 @@ enum lpsift_kernel {
     LPSIFT_KERNEL_SCORE = 9,           /* learned scorer inference */
     LPSIFT_KERNEL_PRUNE = 10,          /* top-k selection of keypoint slots */
     LPSIFT_KERNEL_TRAIN = 11,          /* scorer training step (both kernels) */
-    LPSIFT_KERNEL_COUNT = 12
+    LPSIFT_KERNEL_RANSAC = 12,         /* batched GPU RANSAC (all three kernels) */
+    LPSIFT_KERNEL_COUNT = 13
 };
 
 /* Learned keypoint scorer: MLP 258 -> 64 -> 64 -> 1 (ReLU), parameters as one
@@ -296,6 +297,42 @@ int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float*
                       const int32_t* candidates, int32_t n_candidates, int32_t reps,
                       void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                       float* const* d2, float* ms, int32_t* best, void* stream);
+
+/* Batched RANSAC on the GPU (Sec. 2.5, Eq. 7), FP64, for match lists
+ * written by lpsift_match. For pair p: the accepted matches of match[p]
+ * (nq[p] queries; query i is slot selA[p][i] of image A, or slot i when selA
+ * is null; registered row j is slot selB[p][j] of image B, or slot j) are
+ * compacted in query order into slotA[p], slotB[p] (first stats[3p] entries);
+ * hypotheses are homographies (h33 = 1) through 4 of them, drawn from the
+ * uniforms: slot s of hypothesis h takes the first try t whose
+ * floor(u[h][s][t] * n) is not yet taken (a hypothesis without 4 distinct
+ * indices, or with 3 nearly collinear points in either image, is skipped);
+ * the hypothesis with the most inliers (one-way reprojection error < thresh;
+ * earliest on ties) is refitted by least squares over its inliers (Hartley
+ * coordinates) and inlier[p][k] marks the inliers of that final H.
+ *  kpA, kpB   host arrays of n_pairs keypoint buffers (x, y used)
+ *  selA, selB host arrays of n_pairs device int32 pointers, or null
+ *  match      host array of n_pairs device int32 pointers [nq[p]]
+ *  H          device double [n_pairs][9] (zeros when no hypothesis is valid)
+ *  stats      device int32 [n_pairs][3]: matches, inliers, best hypothesis (-1)
+ *  uniforms   device double [n_iter][4][tries] in [0, 1), shared by all pairs
+ * Match and slot lists must hold valid indices (as written by lpsift_match
+ * and lpsift_prune). Errors: EINVAL, ECAPACITY (workspace), EHIP. */
+typedef struct lpsift_ransac_params {
+    int32_t n_iter;          /* hypotheses, 0 .. 1048576 */
+    int32_t tries;           /* uniforms per slot, 1 .. 64 */
+    double thresh;           /* inlier threshold in pixels, > 0 */
+    const double* uniforms;
+} lpsift_ransac_params;
+
+size_t lpsift_ransac_workspace_size(const int64_t* nq, int32_t n_pairs, int32_t n_iter);
+
+int lpsift_ransac(const lpsift_keypoints* kpA, const lpsift_keypoints* kpB,
+                  const int32_t* const* selA, const int32_t* const* selB,
+                  const int32_t* const* match, const int64_t* nq, int32_t n_pairs,
+                  const lpsift_ransac_params* rp, void* workspace, size_t ws_bytes,
+                  int32_t* const* slotA, int32_t* const* slotB, uint8_t* const* inlier,
+                  double* H, int32_t* stats, void* stream);
 
 /* Kernel timing, a profiling aid. lpsift_timing_enable(1) resets the sums
  * and makes every later launch of the kernels listed in lpsift_kernel bracket

@@ -46,6 +46,11 @@ class lpsift_keypoints(ctypes.Structure):
                 ("contrast", c_vp), ("capacity", c_i64)]
 
 
+class lpsift_ransac_params(ctypes.Structure):
+    _fields_ = [("n_iter", ctypes.c_int32), ("tries", ctypes.c_int32), ("thresh", ctypes.c_double),
+                ("uniforms", ctypes.c_void_p)]
+
+
 class lpsift_match_params(ctypes.Structure):
     _fields_ = [("ratio", c_f64), ("abs_thresh", c_f32), ("precision", c_i32),
                 ("b_chunks", c_i32), ("stats", c_vp)]
@@ -55,7 +60,8 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_describe_workspace_size", "lpsift_describe", "lpsift_match_workspace_size",
            "lpsift_match", "lpsift_match_tune", "lpsift_timing_enable", "lpsift_timing_read",
            "lpsift_describe_selected", "lpsift_score", "lpsift_prune", "lpsift_scorer_gather",
-           "lpsift_scorer_train_workspace_size", "lpsift_scorer_train_step", "lpsift_ransac_host")
+           "lpsift_scorer_train_workspace_size", "lpsift_scorer_train_step", "lpsift_ransac_host",
+           "lpsift_ransac_workspace_size", "lpsift_ransac")
 
 _lib = None
 
@@ -122,6 +128,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_scorer_train_step.restype = ctypes.c_int
     lib.lpsift_scorer_train_step.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp,
                                              c_i64, c_f32, c_vp, ctypes.c_size_t, c_vp, c_vp]
+    lib.lpsift_ransac_workspace_size.restype = ctypes.c_size_t
+    lib.lpsift_ransac_workspace_size.argtypes = [P(c_i64), c_i32, c_i32]
+    lib.lpsift_ransac.restype = ctypes.c_int
+    lib.lpsift_ransac.argtypes = [P(lpsift_keypoints), P(lpsift_keypoints), P(c_vp), P(c_vp), P(c_vp),
+                                  P(c_i64), c_i32, P(lpsift_ransac_params), c_vp, ctypes.c_size_t,
+                                  P(c_vp), P(c_vp), P(c_vp), c_vp, c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -378,7 +390,7 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
 
 
 KERNELS = ("detect", "gradient", "describe", "match_norms", "match_fp32", "match_split",
-           "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train")
+           "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train", "ransac")
 SCORER_PARAMS = 20801
 
 
@@ -511,6 +523,42 @@ def features(images, params: Params, stream=None):
     kps = detect(images, params, stream=stream)
     theta, desc = describe(images, kps, params, stream=stream)
     return kps, theta, desc
+
+
+def ransac_gpu(kpA, kpB, matches, uniforms, thresh: float = 3.0, selA=None, selB=None,
+               workspace=None, stream=None):
+    """Batched RANSAC on the device for match lists of lpsift_match.
+    kpA, kpB: keypoint dicts per pair; matches: int32 tensors [nq]; uniforms:
+    float64 CUDA tensor [n_iter, 4, tries]; selA / selB: optional int32 slot
+    lists per pair. Returns {"H": [n, 9] float64, "stats": [n, 3] int32
+    (matches, inliers, best hypothesis), "slotA", "slotB", "inlier"} (the
+    per-pair lists hold stats[p, 0] valid entries)."""
+    import torch
+    lib = load()
+    n = len(matches)
+    dev = matches[0].device
+    if uniforms.dtype != torch.float64 or uniforms.dim() != 3 or uniforms.shape[1] != 4 \
+            or not uniforms.is_contiguous():
+        raise ValueError("uniforms must be a contiguous float64 tensor [n_iter, 4, tries]")
+    nq = [int(m.numel()) for m in matches]
+    rp = lpsift_ransac_params()
+    rp.n_iter, rp.tries, rp.thresh = int(uniforms.shape[0]), int(uniforms.shape[2]), float(thresh)
+    rp.uniforms = uniforms.data_ptr()
+    need = int(lib.lpsift_ransac_workspace_size((c_i64 * n)(*nq), n, rp.n_iter))
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    slotA = [torch.empty(q, dtype=torch.int32, device=dev) for q in nq]
+    slotB = [torch.empty(q, dtype=torch.int32, device=dev) for q in nq]
+    inl = [torch.empty(q, dtype=torch.uint8, device=dev) for q in nq]
+    H = torch.zeros((n, 9), dtype=torch.float64, device=dev)
+    stats = torch.zeros((n, 3), dtype=torch.int32, device=dev)
+    ptr = lambda ts: (c_vp * n)(*[t.data_ptr() for t in ts])
+    _check("lpsift_ransac", lib.lpsift_ransac(
+        _kps(kpA), _kps(kpB), None if selA is None else ptr(selA),
+        None if selB is None else ptr(selB), ptr(matches), (c_i64 * n)(*nq), n, ctypes.byref(rp),
+        workspace.data_ptr(), workspace.numel(), ptr(slotA), ptr(slotB), ptr(inl), H.data_ptr(),
+        stats.data_ptr(), _stream(stream)))
+    return {"H": H, "stats": stats, "slotA": slotA, "slotB": slotB, "inlier": inl}
 
 
 def ransac(xyA, xyB, samples, thresh: float = 3.0):

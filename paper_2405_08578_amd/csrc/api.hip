@@ -370,6 +370,74 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
     return launch_match_pairs(io.data(), n_pairs, mp, static_cast<hipStream_t>(stream));
 }
 
+size_t lpsift_ransac_workspace_size(const int64_t* nq, int32_t n_pairs, int32_t n_iter)
+{
+    if (!nq || n_pairs < 1 || n_iter < 0 || n_iter > (1 << 20)) return 0;
+    size_t b = 0;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (nq[i] < 0 || nq[i] > INT32_MAX) return 0;
+        b += align_up(ransac_workspace_bytes(nq[i], n_iter), 256);
+    }
+    return b;
+}
+
+int lpsift_ransac(const lpsift_keypoints* kpA, const lpsift_keypoints* kpB,
+                  const int32_t* const* selA, const int32_t* const* selB,
+                  const int32_t* const* match, const int64_t* nq, int32_t n_pairs,
+                  const lpsift_ransac_params* rp, void* workspace, size_t ws_bytes,
+                  int32_t* const* slotA, int32_t* const* slotB, uint8_t* const* inlier,
+                  double* H, int32_t* stats, void* stream)
+{
+    if (!kpA || !kpB || !match || !nq || n_pairs < 1 || !rp || !slotA || !slotB || !inlier ||
+        !H || !stats || !workspace)
+        return LPSIFT_EINVAL;
+    if (rp->n_iter < 0 || rp->n_iter > (1 << 20) || rp->tries < 1 || rp->tries > 64 ||
+        !(rp->thresh > 0.0) || !std::isfinite(rp->thresh) || (rp->n_iter > 0 && !rp->uniforms))
+        return LPSIFT_EINVAL;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (nq[i] < 0 || nq[i] > INT32_MAX) return LPSIFT_EINVAL;
+        if (nq[i] > 0 && (!kpA[i].x || !kpA[i].y || !kpB[i].x || !kpB[i].y || !match[i] ||
+                          !slotA[i] || !slotB[i] || !inlier[i]))
+            return LPSIFT_EINVAL;
+        if (selA && nq[i] > 0 && !selA[i]) return LPSIFT_EINVAL;
+        if (selB && !selB[i]) return LPSIFT_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    if (ws_bytes < lpsift_ransac_workspace_size(nq, n_pairs, rp->n_iter)) return LPSIFT_ECAPACITY;
+    char* ws = static_cast<char*>(workspace);
+    for (int b0 = 0; b0 < n_pairs; b0 += kRansacPairs) {
+        const int nb = (n_pairs - b0 < kRansacPairs) ? n_pairs - b0 : kRansacPairs;
+        RansacBatch b{};
+        b.n = nb;
+        b.n_iter = rp->n_iter;
+        b.tries = rp->tries;
+        b.thresh2 = rp->thresh * rp->thresh;
+        b.u = rp->uniforms;
+        for (int k = 0; k < nb; ++k) {
+            const int i = b0 + k;
+            RansacPair& P = b.p[k];
+            P.ax = kpA[i].x;
+            P.ay = kpA[i].y;
+            P.bx = kpB[i].x;
+            P.by = kpB[i].y;
+            P.selA = selA ? selA[i] : nullptr;
+            P.selB = selB ? selB[i] : nullptr;
+            P.match = match[i];
+            P.nq = nq[i];
+            ransac_layout(ws, nq[i], rp->n_iter, P);
+            ws += align_up(ransac_workspace_bytes(nq[i], rp->n_iter), 256);
+            P.slotA = slotA[i];
+            P.slotB = slotB[i];
+            P.inlier = inlier[i];
+            P.H = H + 9 * (int64_t)i;
+            P.stats = stats + 3 * (int64_t)i;
+        }
+        const int st = launch_ransac(b, static_cast<hipStream_t>(stream));
+        if (st != LPSIFT_OK) return st;
+    }
+    return LPSIFT_OK;
+}
+
 int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float* const* descB,
                       const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
                       const int32_t* candidates, int32_t n_candidates, int32_t reps,

@@ -184,4 +184,41 @@ struct TrainArgs {
 size_t train_workspace_bytes(int64_t batch);
 int launch_train(TrainArgs args, hipStream_t s);
 
+// ---- batched GPU RANSAC ----
+
+constexpr int kRansacPairs = 16;
+
+struct RansacPair {
+    const int32_t* ax;        // keypoint coordinates of image A and image B
+    const int32_t* ay;
+    const int32_t* bx;
+    const int32_t* by;
+    const int32_t* selA;      // optional slot lists (descriptor row -> slot)
+    const int32_t* selB;
+    const int32_t* match;     // [nq]: registered row or -1
+    int64_t nq;
+    double* pa;               // workspace: compacted points [nq][2]
+    double* pb;
+    int32_t* count;           // workspace: number of accepted matches
+    int32_t* bestc;           // workspace: per hypothesis block (inliers, hypothesis)
+    double* bestH;            // workspace: per hypothesis block, its H
+    int32_t* slotA;           // outputs [nq] (first count entries)
+    int32_t* slotB;
+    uint8_t* inlier;
+    double* H;                // output [9]
+    int32_t* stats;           // output [3]: matches, inliers, best hypothesis
+};
+struct RansacBatch {
+    int32_t n;
+    int32_t n_iter;
+    int32_t n_blocks;
+    int32_t tries;
+    double thresh2;
+    const double* u;          // [n_iter][4][tries]
+    RansacPair p[kRansacPairs];
+};
+size_t ransac_workspace_bytes(int64_t nq, int32_t n_iter);
+void ransac_layout(void* ws, int64_t nq, int32_t n_iter, RansacPair& p);
+int launch_ransac(RansacBatch& b, hipStream_t s);
+
 }  // namespace lpsift

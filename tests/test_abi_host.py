@@ -256,3 +256,27 @@ def test_scorer_entry_validation(lib):
     assert step(lr=0.0) == lp.LPSIFT_EINVAL
     assert step(lr=math.nan) == lp.LPSIFT_EINVAL
     assert step(wsb=wsz - 1) == lp.LPSIFT_ECAPACITY
+
+
+def test_ransac_gpu_validation(lib):
+    arr = lambda *v: (ctypes.c_void_p * len(v))(*v)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    k = (lp.lpsift_keypoints * 1)(kps(100))
+    need = lib.lpsift_ransac_workspace_size(i64(1000), 1, 2000)
+    assert need > 2 * 1000 * 16
+    assert lib.lpsift_ransac_workspace_size(i64(-1), 1, 10) == 0
+    assert lib.lpsift_ransac_workspace_size(i64(10), 1, (1 << 20) + 1) == 0
+
+    def call(n_iter=2000, tries=8, thresh=3.0, u=FAKE, wsb=need, ws=0x100000, nq=1000):
+        rp = lp.lpsift_ransac_params(n_iter, tries, thresh, u)
+        return lib.lpsift_ransac(k, k, None, None, arr(FAKE), i64(nq), 1, ctypes.byref(rp), ws, wsb,
+                                 arr(FAKE), arr(FAKE), arr(FAKE), FAKE, FAKE, None)
+    assert call(wsb=need - 1) == lp.LPSIFT_ECAPACITY
+    assert call(tries=0) == lp.LPSIFT_EINVAL
+    assert call(tries=65) == lp.LPSIFT_EINVAL
+    assert call(thresh=0.0) == lp.LPSIFT_EINVAL
+    assert call(thresh=math.inf) == lp.LPSIFT_EINVAL
+    assert call(u=None) == lp.LPSIFT_EINVAL
+    assert call(n_iter=-1) == lp.LPSIFT_EINVAL
+    assert call(ws=0x100000 + 8) == lp.LPSIFT_EINVAL
+    assert call(nq=-5) == lp.LPSIFT_EINVAL
