@@ -526,7 +526,7 @@ def features(images, params: Params, stream=None):
 
 
 def ransac_gpu(kpA, kpB, matches, uniforms, thresh: float = 3.0, selA=None, selB=None,
-               workspace=None, stream=None):
+               workspace=None, stream=None, out=None):
     """Batched RANSAC on the device for match lists of lpsift_match.
     kpA, kpB: keypoint dicts per pair; matches: int32 tensors [nq]; uniforms:
     float64 CUDA tensor [n_iter, 4, tries]; selA / selB: optional int32 slot
@@ -547,18 +547,20 @@ def ransac_gpu(kpA, kpB, matches, uniforms, thresh: float = 3.0, selA=None, selB
     need = int(lib.lpsift_ransac_workspace_size((c_i64 * n)(*nq), n, rp.n_iter))
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
-    slotA = [torch.empty(q, dtype=torch.int32, device=dev) for q in nq]
-    slotB = [torch.empty(q, dtype=torch.int32, device=dev) for q in nq]
-    inl = [torch.empty(q, dtype=torch.uint8, device=dev) for q in nq]
-    H = torch.zeros((n, 9), dtype=torch.float64, device=dev)
-    stats = torch.zeros((n, 3), dtype=torch.int32, device=dev)
+    if out is None:
+        out = {"slotA": [torch.empty(q, dtype=torch.int32, device=dev) for q in nq],
+               "slotB": [torch.empty(q, dtype=torch.int32, device=dev) for q in nq],
+               "inlier": [torch.empty(q, dtype=torch.uint8, device=dev) for q in nq],
+               "H": torch.zeros((n, 9), dtype=torch.float64, device=dev),
+               "stats": torch.zeros((n, 3), dtype=torch.int32, device=dev)}
+    slotA, slotB, inl, H, stats = out["slotA"], out["slotB"], out["inlier"], out["H"], out["stats"]
     ptr = lambda ts: (c_vp * n)(*[t.data_ptr() for t in ts])
     _check("lpsift_ransac", lib.lpsift_ransac(
         _kps(kpA), _kps(kpB), None if selA is None else ptr(selA),
         None if selB is None else ptr(selB), ptr(matches), (c_i64 * n)(*nq), n, ctypes.byref(rp),
         workspace.data_ptr(), workspace.numel(), ptr(slotA), ptr(slotB), ptr(inl), H.data_ptr(),
         stats.data_ptr(), _stream(stream)))
-    return {"H": H, "stats": stats, "slotA": slotA, "slotB": slotB, "inlier": inl}
+    return out
 
 
 def ransac(xyA, xyB, samples, thresh: float = 3.0):

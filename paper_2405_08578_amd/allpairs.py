@@ -8,7 +8,8 @@ so that one step is three library calls (detect, describe, match) that
 allocate nothing and never synchronise. The step can run eagerly or be
 captured once into a HIP graph (torch.cuda.CUDAGraph) and replayed: the
 launch sequence is fixed by the image shapes, and replays read the images from
-the same device buffers.
+the same device buffers. Optionally the step ends with the batched GPU RANSAC
+of every pair (the pairwise homographies of the mosaic, Sec. 4).
 """
 from __future__ import annotations
 
@@ -16,7 +17,8 @@ import math
 from typing import List, Optional, Tuple
 
 from . import (DESC_DIM, Params, describe, describe_workspace_size, detect, empty_keypoints,
-               match, match_params, match_workspace_size, num_keypoints)
+               load, match, match_params, match_workspace_size,
+               num_keypoints, ransac_gpu)
 
 
 def pair_list(n: int) -> List[Tuple[int, int]]:
@@ -25,7 +27,11 @@ def pair_list(n: int) -> List[Tuple[int, int]]:
 
 class AllPairs:
     def __init__(self, images, params: Params, precision: int = 0, b_chunks: int = 0,
-                 ratio: float = 0.8, abs_thresh: float = math.inf):
+                 ratio: float = 0.8, abs_thresh: float = math.inf, ransac_uniforms=None,
+                 ransac_thresh: float = 3.0):
+        """ransac_uniforms: optional float64 CUDA tensor [n_iter, 4, tries];
+        when given, every step ends with the batched GPU RANSAC of all pairs
+        (self.ransac: H [pairs, 9], stats [pairs, 3], slot and inlier lists)."""
         import torch
         if len(images) < 2:
             raise ValueError("need at least two images")
@@ -55,6 +61,16 @@ class AllPairs:
                      "d2": torch.empty(self.n_kp[i], dtype=torch.float32, device=dev)}
                     for i, _ in self.pairs]
         self.graph = None
+        self.ransac = None
+        self.ransac_uniforms = ransac_uniforms
+        self.ransac_thresh = ransac_thresh
+        if ransac_uniforms is not None:
+            import ctypes
+            nq = [self.n_kp[i] for i, _ in self.pairs]
+            n = len(nq)
+            need = int(load().lpsift_ransac_workspace_size((ctypes.c_int64 * n)(*nq), n,
+                                                           int(ransac_uniforms.shape[0])))
+            self.rws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
 
     @property
     def megapixels(self) -> float:
@@ -69,6 +85,12 @@ class AllPairs:
               ratio=self.ratio, abs_thresh=self.abs_thresh, precision=self.precision,
               b_chunks=self.b_chunks, workspace=self.mws, out=self.out, stream=stream,
               stats=self.stats)
+        if self.ransac_uniforms is not None:
+            self.ransac = ransac_gpu([self.kps[i] for i, _ in self.pairs],
+                                     [self.kps[j] for _, j in self.pairs],
+                                     [o["match"] for o in self.out], self.ransac_uniforms,
+                                     self.ransac_thresh, workspace=self.rws, stream=stream,
+                                     out=self.ransac)
 
     def capture(self, warmup: int = 1):
         """Capture one step into a graph (after `warmup` eager steps on a side

@@ -1,0 +1,135 @@
+"""Mosaic registration of an unordered image set (Sec. 4, Fig. 8).
+
+The pairwise homographies of all image pairs form H_M; a pair is stitchable
+when its RANSAC keeps at least `min_inliers` inliers and at least `min_share`
+of its matches (the paper does not say when an H_M entry is zero; on
+self-similar textures many pairs that do not overlap still pass the ratio
+test, and a model fitted to them keeps a small share). Rounds (reading of
+Sec. 4, which leaves the joining of later references open):
+  * round 1: the reference is the image with the most stitchable partners
+    (lowest index on ties); it and its partners are placed, each partner with
+    the transform of its pair;
+  * later rounds: the next reference is the unplaced image with the most
+    stitchable partners among the placed images (then the most partners
+    overall, then the lowest index); it joins through its placed partner with
+    the most inliers, and its unplaced partners are placed through it;
+  * an unplaced image with no placed partner is left unregistered.
+Transforms map image pixels to the first reference's pixels. This module is
+host logic on the n x n pairwise results; the pairwise work is the GPU path
+(AllPairs with RANSAC).
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+def pair_transforms(n: int, pairs, H, inliers, matches=None, min_inliers: int = 12,
+                    min_share: float = 0.05):
+    """Stitchable-pair matrix from per-pair results: T[i][j] maps image i to
+    image j (pair (i, j) gives H: i -> j and its inverse), W[i][j] inliers.
+    A pair is stitchable when its RANSAC keeps at least min_inliers inliers
+    and at least min_share of its matches (a model fitted to chance matches
+    keeps few of many)."""
+    T = [[None] * n for _ in range(n)]
+    W = np.zeros((n, n), np.int64)
+    if matches is None:
+        matches = [0] * len(pairs)
+    for (i, j), h, c, m in zip(pairs, H, inliers, matches):
+        h = np.asarray(h, np.float64).reshape(3, 3)
+        if c < min_inliers or c < min_share * m:
+            continue
+        if not np.all(np.isfinite(h)) or abs(np.linalg.det(h)) < 1e-12:
+            continue
+        T[i][j] = h / h[2, 2]
+        hi = np.linalg.inv(h)
+        T[j][i] = hi / hi[2, 2]
+        W[i, j] = W[j, i] = int(c)
+    return T, W
+
+
+def register(n: int, T, W) -> Dict[str, object]:
+    """Rounds of Sec. 4 over the stitchable-pair matrix; returns transforms
+    (image -> reference pixels, None if unregistered), the rounds (reference
+    and images placed), the placement links (image, image it was placed
+    through) and the unregistered images."""
+    deg = (W > 0).sum(axis=1)
+    G: List[Optional[np.ndarray]] = [None] * n
+    rounds = []
+    if n == 0:
+        return {"G": G, "rounds": rounds, "unregistered": [], "links": []}
+    ref = int(np.lexsort((np.arange(n), -deg))[0])
+    G[ref] = np.eye(3)
+    placed = [ref]
+    links = []
+    for j in range(n):
+        if j != ref and W[ref, j] > 0:
+            G[j] = T[j][ref]
+            placed.append(j)
+            links.append((j, ref))
+    rounds.append({"reference": ref, "placed": placed[:]})
+    while True:
+        left = [u for u in range(n) if G[u] is None]
+        if not left:
+            break
+        score = [(int(sum(W[u, p] > 0 for p in range(n) if G[p] is not None)), int(deg[u]), -u)
+                 for u in left]
+        best = max(range(len(left)), key=lambda k: score[k])
+        if score[best][0] == 0:
+            break
+        u = left[best]
+        via = max((p for p in range(n) if G[p] is not None and W[u, p] > 0),
+                  key=lambda p: (W[u, p], -p))
+        G[u] = G[via] @ T[u][via]
+        links.append((u, via))
+        now = [u]
+        for j in range(n):
+            if G[j] is None and W[u, j] > 0:
+                G[j] = G[u] @ T[j][u]
+                now.append(j)
+                links.append((j, u))
+        rounds.append({"reference": u, "via": via, "placed": now})
+    for k in range(n):
+        if G[k] is not None:
+            G[k] = G[k] / G[k][2, 2]
+    return {"G": G, "rounds": rounds, "unregistered": [k for k in range(n) if G[k] is None],
+            "reference": ref, "links": links}
+
+
+def corner_error(G: np.ndarray, G_true: np.ndarray, w: int, h: int) -> float:
+    """Largest distance between the image corners mapped by G and by G_true."""
+    c = np.array([[0, 0, 1], [w - 1, 0, 1], [w - 1, h - 1, 1], [0, h - 1, 1]], np.float64)
+    a = c @ np.asarray(G).T
+    b = c @ np.asarray(G_true).T
+    return float(np.max(np.linalg.norm(a[:, :2] / a[:, 2:] - b[:, :2] / b[:, 2:], axis=1)))
+
+
+def seam_errors(G, G_true, shapes, step: int = 64) -> Dict[tuple, float]:
+    """Alignment error of every truly overlapping pair of registered images:
+    points of image i on a `step` grid that the true transforms place inside
+    image j are mapped by both estimated transforms into the reference frame;
+    the largest distance between the two mappings, per pair (i, j)."""
+    out = {}
+    n = len(G)
+    for i in range(n):
+        if G[i] is None:
+            continue
+        h, w = shapes[i]
+        ys, xs = np.mgrid[0:h:step, 0:w:step]
+        P = np.c_[xs.ravel(), ys.ravel(), np.ones(xs.size)].astype(np.float64)
+        for j in range(n):
+            if j == i or G[j] is None:
+                continue
+            Tij = np.linalg.inv(G_true[j]) @ G_true[i]          # true i -> j
+            q = P @ Tij.T
+            q = q[:, :2] / q[:, 2:]
+            hj, wj = shapes[j]
+            inside = (q[:, 0] >= 0) & (q[:, 0] <= wj - 1) & (q[:, 1] >= 0) & (q[:, 1] <= hj - 1)
+            if inside.sum() < 4:
+                continue
+            a = P[inside] @ np.asarray(G[i]).T
+            b = np.c_[q[inside], np.ones(inside.sum())] @ np.asarray(G[j]).T
+            d = np.linalg.norm(a[:, :2] / a[:, 2:] - b[:, :2] / b[:, 2:], axis=1)
+            out[(i, j)] = float(d.max())
+    return out
