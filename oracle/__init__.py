@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline import this package; the product library never does, and the oracle
 never imports the product. The arithmetic lives in ``lpsift_oracle.c`` (plain
-C, double precision), ``ransac.py`` and ``scorer.py`` (NumPy, double
+C, double precision), ``ransac.py``, ``scorer.py`` and ``quantized.py`` (NumPy,
+double
 precision); this module only marshals arrays.
 
 Pins (what each function is checked against, in tests/test_oracle_*.py):
@@ -15,6 +16,8 @@ Pins (what each function is checked against, in tests/test_oracle_*.py):
                binning of a ramp, rotation and gain invariance, unit norm
   match        SciPy k-d tree / cdist cross-check, hand-built exact cases
   ransac       exact correspondences (DLT recovers H), known outlier sets
+  quantized    uint8 quantisation closed forms, integer distances vs cdist,
+               the (4, 5) ratio case, duplicate rows
   scorer       padded-slice patches, torch FP64 autograd and finite
                differences for the MLP gradient, Adam's closed-form first
                step and torch's Adam, brute-force sort for the prune
