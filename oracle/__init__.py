@@ -4,8 +4,7 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline import this package; the product library never does, and the oracle
 never imports the product. The arithmetic lives in ``lpsift_oracle.c`` (plain
 C, double precision), ``ransac.py``, ``scorer.py`` and ``quantized.py`` (NumPy,
-double
-precision); this module only marshals arrays.
+double precision); this module only marshals arrays.
 
 Pins (what each function is checked against, in tests/test_oracle_*.py):
   detect       brute force on tiny images, Eq. 1 in exact rational arithmetic,
