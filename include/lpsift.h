@@ -57,7 +57,9 @@ enum lpsift_kernel {
     LPSIFT_KERNEL_PRUNE = 10,          /* top-k selection of keypoint slots */
     LPSIFT_KERNEL_TRAIN = 11,          /* scorer training step (both kernels) */
     LPSIFT_KERNEL_RANSAC = 12,         /* batched GPU RANSAC (all three kernels) */
-    LPSIFT_KERNEL_COUNT = 13
+    LPSIFT_KERNEL_MATCH_U8 = 13,       /* uint8 int8-matrix-core contraction with top-2 */
+    LPSIFT_KERNEL_MATCH_U8_AUX = 14,   /* uint8 candidate terms and final merge */
+    LPSIFT_KERNEL_COUNT = 15
 };
 
 /* Learned keypoint scorer: MLP 258 -> 64 -> 64 -> 1 (ReLU), parameters as one
@@ -297,6 +299,35 @@ int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float*
                       const int32_t* candidates, int32_t n_candidates, int32_t reps,
                       void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                       float* const* d2, float* ms, int32_t* best, void* stream);
+
+/* uint8 descriptors, the stored form of SIFT implementations (not fixed by the
+ * paper; Sec. 2.3 descriptors are unit-norm FP32 vectors).
+ * lpsift_quantize_u8: q[i][k] = min(255, rint(512 desc[i][k])) (round half to
+ * even; negative values give 0) for n descriptors. desc 16-byte aligned, q
+ * 4-byte aligned. Errors: EINVAL (null or misaligned pointer, n < 0), EHIP. */
+int lpsift_quantize_u8(const float* desc, int64_t n, uint8_t* q, void* stream);
+
+/* Device workspace, in bytes, of lpsift_match_u8 for nA queries and nB
+ * registered descriptors (0 for negative counts). */
+size_t lpsift_match_u8_workspace_size(int64_t nA, int64_t nB);
+
+/* Exact matching of uint8 descriptors (Sec. 2.4, Eq. 6 on integer squared
+ * distances D = sum (qa - qb)^2, computed exactly on the int8 matrix cores).
+ * For each query i: j1 = the registered row with the smallest D (lowest index
+ * on ties), D1 its distance, D2 the smallest over the other rows.
+ * d1[i] = sqrt(D1) / 512, d2[i] = sqrt(D2) / 512 (+inf when nB < 2; both +inf
+ * when nB = 0), rounded from double to float. match[i] = j1 when
+ * (ratio = +inf or sqrt(D1) < ratio sqrt(D2)) and sqrt(D1) / 512 < abs_thresh
+ * (the test is taken in double), else -1.
+ *  qA, qB     device uint8 [n][128], 16-byte aligned
+ *  nA, nB     0 .. 2^31 - 1
+ *  workspace  device, 256-byte aligned, >= lpsift_match_u8_workspace_size
+ *  match, d1, d2  device int32 / float [nA]
+ * Errors: EINVAL (null or misaligned pointer, bad count, ratio or abs_thresh
+ * not > 0), ECAPACITY (workspace), EHIP. */
+int lpsift_match_u8(const uint8_t* qA, int64_t nA, const uint8_t* qB, int64_t nB, double ratio,
+                    float abs_thresh, void* workspace, size_t ws_bytes, int32_t* match,
+                    float* d1, float* d2, void* stream);
 
 /* Batched RANSAC on the GPU (Sec. 2.5, Eq. 7), FP64, for match lists
  * written by lpsift_match. For pair p: the accepted matches of match[p]

@@ -61,7 +61,8 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_match", "lpsift_match_tune", "lpsift_timing_enable", "lpsift_timing_read",
            "lpsift_describe_selected", "lpsift_score", "lpsift_prune", "lpsift_scorer_gather",
            "lpsift_scorer_train_workspace_size", "lpsift_scorer_train_step", "lpsift_ransac_host",
-           "lpsift_ransac_workspace_size", "lpsift_ransac")
+           "lpsift_ransac_workspace_size", "lpsift_ransac", "lpsift_quantize_u8",
+           "lpsift_match_u8_workspace_size", "lpsift_match_u8")
 
 _lib = None
 
@@ -134,6 +135,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_ransac.argtypes = [P(lpsift_keypoints), P(lpsift_keypoints), P(c_vp), P(c_vp), P(c_vp),
                                   P(c_i64), c_i32, P(lpsift_ransac_params), c_vp, ctypes.c_size_t,
                                   P(c_vp), P(c_vp), P(c_vp), c_vp, c_vp, c_vp]
+    lib.lpsift_quantize_u8.restype = ctypes.c_int
+    lib.lpsift_quantize_u8.argtypes = [c_vp, c_i64, c_vp, c_vp]
+    lib.lpsift_match_u8_workspace_size.restype = ctypes.c_size_t
+    lib.lpsift_match_u8_workspace_size.argtypes = [c_i64, c_i64]
+    lib.lpsift_match_u8.restype = ctypes.c_int
+    lib.lpsift_match_u8.argtypes = [c_vp, c_i64, c_vp, c_i64, c_f64, c_f32, c_vp,
+                                    ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -327,6 +335,49 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
     return out
 
 
+def quantize_u8(desc, out=None, stream=None):
+    """uint8 form of descriptors: min(255, rint(512 d)) per element."""
+    import torch
+    if desc.dtype != torch.float32 or desc.dim() != 2 or desc.shape[1] != DESC_DIM \
+            or not desc.is_cuda or not desc.is_contiguous():
+        raise ValueError("descriptors must be contiguous float32 CUDA tensors [n, 128]")
+    if out is None:
+        out = torch.empty(desc.shape, dtype=torch.uint8, device=desc.device)
+    _check("lpsift_quantize_u8", load().lpsift_quantize_u8(desc.data_ptr(), desc.shape[0],
+                                                           out.data_ptr(), _stream(stream)))
+    return out
+
+
+def match_u8_workspace_size(nA: int, nB: int) -> int:
+    return int(load().lpsift_match_u8_workspace_size(nA, nB))
+
+
+def match_u8(qA, qB, ratio: float = 0.8, abs_thresh: float = math.inf, workspace=None,
+             out=None, stream=None) -> Dict[str, "object"]:
+    """Exact nearest neighbour of every row of qA among qB (uint8 [n, 128]
+    CUDA tensors) on integer squared distances, with the ratio test; d1, d2 are
+    sqrt(D) / 512."""
+    import torch
+    for t in (qA, qB):
+        if t.dtype != torch.uint8 or t.dim() != 2 or t.shape[1] != DESC_DIM or not t.is_cuda \
+                or not t.is_contiguous():
+            raise ValueError("descriptors must be contiguous uint8 CUDA tensors [n, 128]")
+    nA, nB = int(qA.shape[0]), int(qB.shape[0])
+    dev = qA.device
+    if workspace is None:
+        workspace = torch.empty(max(match_u8_workspace_size(nA, nB), 256), dtype=torch.uint8,
+                                device=dev)
+    if out is None:
+        out = {"match": torch.empty(nA, dtype=torch.int32, device=dev),
+               "d1": torch.empty(nA, dtype=torch.float32, device=dev),
+               "d2": torch.empty(nA, dtype=torch.float32, device=dev)}
+    _check("lpsift_match_u8", load().lpsift_match_u8(
+        qA.data_ptr(), nA, qB.data_ptr(), nB, ratio, abs_thresh, workspace.data_ptr(),
+        workspace.numel(), out["match"].data_ptr(), out["d1"].data_ptr(), out["d2"].data_ptr(),
+        _stream(stream)))
+    return out
+
+
 TUNE_CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16)
 
 
@@ -390,7 +441,8 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
 
 
 KERNELS = ("detect", "gradient", "describe", "match_norms", "match_fp32", "match_split",
-           "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train", "ransac")
+           "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train", "ransac",
+           "match_u8", "match_u8_aux")
 SCORER_PARAMS = 20801
 
 

@@ -370,6 +370,37 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
     return launch_match_pairs(io.data(), n_pairs, mp, static_cast<hipStream_t>(stream));
 }
 
+int lpsift_quantize_u8(const float* desc, int64_t n, uint8_t* q, void* stream)
+{
+    if (n < 0 || n > INT32_MAX) return LPSIFT_EINVAL;
+    if (n > 0 && (!desc || !q)) return LPSIFT_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(desc) & 15u) || (reinterpret_cast<uintptr_t>(q) & 3u))
+        return LPSIFT_EINVAL;
+    return launch_quantize_u8(desc, n, q, static_cast<hipStream_t>(stream));
+}
+
+size_t lpsift_match_u8_workspace_size(int64_t nA, int64_t nB)
+{
+    if (nA < 0 || nB < 0 || nA > INT32_MAX || nB > INT32_MAX) return 0;
+    return match_u8_workspace_bytes(nA, nB);
+}
+
+int lpsift_match_u8(const uint8_t* qA, int64_t nA, const uint8_t* qB, int64_t nB, double ratio,
+                    float abs_thresh, void* workspace, size_t ws_bytes, int32_t* match,
+                    float* d1, float* d2, void* stream)
+{
+    if (nA < 0 || nB < 0 || nA > INT32_MAX || nB > INT32_MAX) return LPSIFT_EINVAL;
+    if (!(ratio > 0.0) || std::isnan(abs_thresh) || !(abs_thresh > 0.0f)) return LPSIFT_EINVAL;
+    if (nA > 0 && (!qA || !match || !d1 || !d2)) return LPSIFT_EINVAL;
+    if (nB > 0 && !qB) return LPSIFT_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(qA) | reinterpret_cast<uintptr_t>(qB)) & 15u)
+        return LPSIFT_EINVAL;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    if (ws_bytes < match_u8_workspace_bytes(nA, nB)) return LPSIFT_ECAPACITY;
+    return launch_match_u8(qA, nA, qB, nB, ratio, abs_thresh, workspace, match, d1, d2,
+                           static_cast<hipStream_t>(stream));
+}
+
 size_t lpsift_ransac_workspace_size(const int64_t* nq, int32_t n_pairs, int32_t n_iter)
 {
     if (!nq || n_pairs < 1 || n_iter < 0 || n_iter > (1 << 20)) return 0;

@@ -217,6 +217,13 @@ struct RansacBatch {
     const double* u;          // [n_iter][4][tries]
     RansacPair p[kRansacPairs];
 };
+// uint8 descriptors (match_u8.hip)
+int launch_quantize_u8(const float* desc, int64_t n, uint8_t* out, hipStream_t stream);
+size_t match_u8_workspace_bytes(int64_t nA, int64_t nB);
+int launch_match_u8(const uint8_t* A, int64_t nA, const uint8_t* B, int64_t nB, double ratio,
+                    float abs_thresh, void* ws, int32_t* match, float* d1, float* d2,
+                    hipStream_t stream);
+
 size_t ransac_workspace_bytes(int64_t nq, int32_t n_iter);
 void ransac_layout(void* ws, int64_t nq, int32_t n_iter, RansacPair& p);
 int launch_ransac(RansacBatch& b, hipStream_t s);

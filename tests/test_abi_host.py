@@ -26,7 +26,7 @@ def lib():
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "lpsift.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(lpsift_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(lpsift_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_exports_every_declared_symbol(lib):
@@ -280,3 +280,36 @@ def test_ransac_gpu_validation(lib):
     assert call(n_iter=-1) == lp.LPSIFT_EINVAL
     assert call(ws=0x100000 + 8) == lp.LPSIFT_EINVAL
     assert call(nq=-5) == lp.LPSIFT_EINVAL
+
+
+def test_u8_entry_validation(lib):
+    A = ctypes.c_void_p(1 << 20)                 # never dereferenced: every call below fails first
+    ws = ctypes.c_void_p(1 << 21)
+    E = lp.LPSIFT_EINVAL
+    assert lib.lpsift_quantize_u8(None, 3, A, None) == E
+    assert lib.lpsift_quantize_u8(A, -1, A, None) == E
+    assert lib.lpsift_quantize_u8(ctypes.c_void_p((1 << 20) + 4), 1, A, None) == E
+    assert lib.lpsift_quantize_u8(A, 1, ctypes.c_void_p((1 << 20) + 2), None) == E
+    assert lib.lpsift_quantize_u8(None, 0, None, None) == lp.LPSIFT_OK    # nothing to do
+    assert lib.lpsift_match_u8_workspace_size(-1, 5) == 0
+    assert lib.lpsift_match_u8_workspace_size(5, 1 << 31) == 0
+    small = lib.lpsift_match_u8_workspace_size(100, 300)
+    big = lib.lpsift_match_u8_workspace_size(60000, 60000)
+    assert 0 < small < big
+
+    def call(qA=A, nA=10, qB=A, nB=10, ratio=0.8, thr=math.inf, w=ws, nbytes=1 << 30, out=A):
+        return lib.lpsift_match_u8(qA, nA, qB, nB, ratio, thr, w, nbytes, out, out, out, None)
+    assert call(nA=-1) == E
+    assert call(nB=1 << 31) == E
+    assert call(ratio=0.0) == E
+    assert call(ratio=math.nan) == E
+    assert call(thr=math.nan) == E
+    assert call(thr=0.0) == E
+    assert call(qA=None) == E
+    assert call(qB=None) == E
+    assert call(out=None) == E
+    assert call(qA=ctypes.c_void_p((1 << 20) + 8)) == E
+    assert call(w=ctypes.c_void_p((1 << 21) + 64)) == E
+    assert call(w=None) == E
+    assert call(nbytes=lib.lpsift_match_u8_workspace_size(10, 10) - 1) == lp.LPSIFT_ECAPACITY
+    assert call(nA=0, qA=None, out=None) == lp.LPSIFT_OK                   # no queries: no launch
