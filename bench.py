@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpix/s detect+describe; pairs/s matched; learned-pruned vs plain, equal inliers"
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0           # GB/s
+PEAK_INT8_MFMA = 5000.0     # TOP/s, MI355X dense int8 matrix
 
 
 def parse():
@@ -463,6 +464,36 @@ def main():
             lowp[name]["queries_rematched_fp32"] = int(stats.item())
         del wsl, outl
     out["low_precision_match"] = lowp
+    # uint8 descriptors (side field): quantise both sets and match them exactly
+    # on the int8 matrix cores
+    qA = torch.empty((n_kp, 128), dtype=torch.uint8, device=dev)
+    qB = torch.empty_like(qA)
+    wsu = torch.empty(lp.match_u8_workspace_size(n_kp, n_kp), dtype=torch.uint8, device=dev)
+    outu = {k: torch.empty_like(v) for k, v in mout[0].items()}
+
+    def u8_call():
+        lp.quantize_u8(desc[0], out=qA, stream=stream)
+        lp.quantize_u8(desc[1], out=qB, stream=stream)
+        lp.match_u8(qA, qB, workspace=wsu, out=outu, stream=stream)
+    for _ in range(max(1, args.warmup)):
+        u8_call()
+    _, ms = timed(u8_call, args.steps, stream)
+    lp.timing_enable(True)
+    timed(u8_call, args.steps, stream)
+    ku = kernel_table(lp.timing_read(), args.steps)
+    lp.timing_enable(False)
+    ku_ms = ku["match_u8"]["ms_per_launch"]
+    tops = flops / (ku_ms * 1e-3) / 1e12
+    out["uint8_exact_match"] = {
+        "ms_quantize_and_match": round(ms, 4),
+        "pairs_per_s": round(1000.0 / (dd_ms + ms), 2),
+        "contraction_ms": round(ku_ms, 4),
+        "merge_and_terms_ms": round(ku["match_u8_aux"]["ms_per_step"], 4),
+        "contraction_int8_tops": round(tops, 1),
+        "frac_of_int8_peak": round(tops / PEAK_INT8_MFMA, 4),
+        "list_agreement_with_fp32": round((outu["match"] == ref).float().mean().item(), 6),
+        "matches": int((outu["match"] >= 0).sum().item())}
+    del qA, qB, wsu, outu
     del kps, theta, desc, ws_d, ws_m, mout
     torch.cuda.empty_cache()
 

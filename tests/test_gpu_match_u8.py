@@ -158,12 +158,12 @@ def test_repeat_call_reuses_workspace(gpu):
 
 
 def test_full_size_sampled(gpu):
-    """42850 x 42850 descriptors (the keypoint slots of a 2600 x 1600 image at
-    L = 16, 32, 64), the launch configuration the benchmark times; about 90
+    """43396 x 43396 descriptors (the keypoint slots of a 2600 x 1600 image at
+    L = 16, 32, 64, 128), the launch configuration the benchmark times; about 90
     sampled queries, among them both sides of several 512-query block edges and
     the last block, against the oracle."""
     import torch
-    n = 42850
+    n = 43396
     a, b = descriptor_sets(n, n, 41)
     say("match_u8 full size", n)
     qa = lp.quantize_u8(to_dev(a, gpu))
@@ -173,5 +173,5 @@ def test_full_size_sampled(gpu):
     ha, hb = qa.cpu().numpy(), qb.cpu().numpy()
     rng = np.random.default_rng(5)
     rows = np.unique(np.r_[rng.integers(0, n, 80), [0, 511, 512, 1023, 1024, n - 1, n - 2,
-                                                     n - 512, 42495, 42496]])
+                                                     n - 512, 43007, 43008]])
     check(r, ha, hb, rows=rows)
