@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline import this package; the product library never does, and the oracle
 never imports the product. The arithmetic lives in ``lpsift_oracle.c`` (plain
-C, double precision), ``ransac.py``, ``scorer.py`` and ``quantized.py`` (NumPy,
-double precision); this module only marshals arrays.
+C, double precision), ``ransac.py``, ``scorer.py``, ``quantized.py`` and
+``multi_orient.py`` (NumPy, double precision); this module only marshals
+arrays.
 
 Pins (what each function is checked against, in tests/test_oracle_*.py):
   detect       brute force on tiny images, Eq. 1 in exact rational arithmetic,
@@ -17,6 +18,9 @@ Pins (what each function is checked against, in tests/test_oracle_*.py):
   ransac       exact correspondences (DLT recovers H), known outlier sets
   quantized    uint8 quantisation closed forms, integer distances vs cdist,
                the (4, 5) ratio case, duplicate rows
+  multi_orient secondary-peak rule on closed-form histograms (threshold,
+               strictness, wrap, order, truncation, parabola), an image with
+               orientations exactly {0, 90} degrees, rot90 equivariance
   scorer       padded-slice patches, torch FP64 autograd and finite
                differences for the MLP gradient, Adam's closed-form first
                step and torch's Adam, brute-force sort for the prune
