@@ -494,6 +494,27 @@ def main():
         "list_agreement_with_fp32": round((outu["match"] == ref).float().mean().item(), 6),
         "matches": int((outu["match"] >= 0).sum().item())}
     del qA, qB, wsu, outu
+
+    # multi-orientation rows (side field): secondary orientations >= 0.8 of
+    # the highest, up to 4 per keypoint; one untimed FP32 match of the rows
+    mo = lp.describe_multi(imgs, kps, P, 4, 0.8, stream=stream)
+    wsmo = torch.empty(lp.describe_multi_workspace_size(imgs, P), dtype=torch.uint8, device=dev)
+    mo_call = lambda: lp.describe_multi(imgs, kps, P, 4, 0.8, workspace=wsmo, out=mo,
+                                        stream=stream)
+    for _ in range(max(1, args.warmup)):
+        mo_call()
+    _, ms_mo = timed(mo_call, args.steps, stream)
+    nr = [int(v) for v in mo["n_rows"].cpu()]
+    mm = lp.match([mo["desc"][0][:nr[0]]], [mo["desc"][1][:nr[1]]], stream=stream)[0]
+    out["multi_orientation"] = {
+        "describe_ms_both_images": round(ms_mo, 4),
+        "single_orientation_describe_ms": round(kt["gradient"]["ms_per_step"] +
+                                                kt["describe"]["ms_per_step"], 4),
+        "rows_per_keypoint": round(sum(nr) / (2 * n_kp), 4),
+        "rows": nr,
+        "matches_fp32": int((mm["match"] >= 0).sum().item()),
+        "matches_single_orientation": n_match}
+    del mo, wsmo, mm
     del kps, theta, desc, ws_d, ws_m, mout
     torch.cuda.empty_cache()
 

@@ -59,7 +59,8 @@ enum lpsift_kernel {
     LPSIFT_KERNEL_RANSAC = 12,         /* batched GPU RANSAC (all three kernels) */
     LPSIFT_KERNEL_MATCH_U8 = 13,       /* uint8 int8-matrix-core contraction with top-2 */
     LPSIFT_KERNEL_MATCH_U8_AUX = 14,   /* uint8 candidate terms and final merge */
-    LPSIFT_KERNEL_COUNT = 15
+    LPSIFT_KERNEL_ORIENT_MULTI = 15,   /* multi-orientation pass and row scan */
+    LPSIFT_KERNEL_COUNT = 16
 };
 
 /* Learned keypoint scorer: MLP 258 -> 64 -> 64 -> 1 (ReLU), parameters as one
@@ -207,6 +208,31 @@ int lpsift_describe_selected(const lpsift_image* imgs, int32_t n_images,
                              const int32_t* const* sel, const int64_t* n_sel, void* workspace,
                              size_t ws_bytes, float* const* theta, float* const* desc,
                              void* stream);
+
+/* Multi-orientation description (the secondary orientations of Lowe's SIFT,
+ * which Sec. 2.3 builds on): each keypoint slot gets its dominant orientation
+ * (exactly lpsift_describe's theta0) and, after it, up to max_orient - 1
+ * further ones: the strict local maxima of the smoothed 36-bin orientation
+ * histogram other than the dominant bin whose height is >= peak_ratio times
+ * the highest (compared in FP32), highest first (lower bin on equal heights),
+ * each refined by the parabola through its bin and the two neighbours. Every
+ * (slot, orientation) gives one descriptor row; rows are compacted in slot
+ * order, a slot's orientations in the order above:
+ *  rows[i][r]   slot of row r (device int32, capacity n_kp[i] * max_orient)
+ *  theta[i][r]  its orientation in radians (device float, same capacity)
+ *  desc[i]      float [capacity][128]
+ *  n_rows[i]    device int64 [n_images], 8-byte aligned: rows written for
+ *               image i (rows beyond it are left untouched)
+ * max_orient 1..4 (1 gives lpsift_describe's rows, one per slot), peak_ratio
+ * in (0, 1] (Lowe: 0.8). Deterministic. Errors: as lpsift_describe, plus
+ * EINVAL for bad max_orient / peak_ratio or a null or misaligned output. */
+size_t lpsift_describe_multi_workspace_size(const lpsift_image* imgs, int32_t n_images,
+                                            const lpsift_params* params);
+int lpsift_describe_multi(const lpsift_image* imgs, int32_t n_images, const lpsift_keypoints* kps,
+                          const lpsift_params* params, int32_t max_orient, float peak_ratio,
+                          void* workspace, size_t ws_bytes, int32_t* const* rows,
+                          float* const* theta, float* const* desc, int64_t* n_rows,
+                          void* stream);
 
 /* Learned keypoint scorer (not part of the paper's method; it ranks the
  * keypoints of Sec. 2.2 so that only the best share is described and matched).

@@ -62,7 +62,8 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_describe_selected", "lpsift_score", "lpsift_prune", "lpsift_scorer_gather",
            "lpsift_scorer_train_workspace_size", "lpsift_scorer_train_step", "lpsift_ransac_host",
            "lpsift_ransac_workspace_size", "lpsift_ransac", "lpsift_quantize_u8",
-           "lpsift_match_u8_workspace_size", "lpsift_match_u8")
+           "lpsift_match_u8_workspace_size", "lpsift_match_u8",
+           "lpsift_describe_multi_workspace_size", "lpsift_describe_multi")
 
 _lib = None
 
@@ -142,6 +143,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_match_u8.restype = ctypes.c_int
     lib.lpsift_match_u8.argtypes = [c_vp, c_i64, c_vp, c_i64, c_f64, c_f32, c_vp,
                                     ctypes.c_size_t, c_vp, c_vp, c_vp, c_vp]
+    lib.lpsift_describe_multi_workspace_size.restype = ctypes.c_size_t
+    lib.lpsift_describe_multi_workspace_size.argtypes = [P(lpsift_image), c_i32, P(lpsift_params)]
+    lib.lpsift_describe_multi.restype = ctypes.c_int
+    lib.lpsift_describe_multi.argtypes = [P(lpsift_image), c_i32, P(lpsift_keypoints),
+                                          P(lpsift_params), c_i32, c_f32, c_vp, ctypes.c_size_t,
+                                          P(c_vp), P(c_vp), P(c_vp), c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -442,7 +449,7 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
 
 KERNELS = ("detect", "gradient", "describe", "match_norms", "match_fp32", "match_split",
            "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train", "ransac",
-           "match_u8", "match_u8_aux")
+           "match_u8", "match_u8_aux", "orient_multi")
 SCORER_PARAMS = 20801
 
 
@@ -470,6 +477,40 @@ def describe_selected(images, kps, params: Params, sel, workspace=None, theta=No
         (c_vp * n)(*[t.data_ptr() for t in theta]), (c_vp * n)(*[t.data_ptr() for t in desc]),
         _stream(stream)))
     return theta, desc
+
+
+def describe_multi_workspace_size(images, params: Params) -> int:
+    return int(load().lpsift_describe_multi_workspace_size(_images(images), len(images),
+                                                           ctypes.byref(params.c())))
+
+
+def describe_multi(images, kps, params: Params, max_orient: int = 4, peak_ratio: float = 0.8,
+                   workspace=None, out=None, stream=None):
+    """Multi-orientation rows of every keypoint slot (dominant orientation
+    first, then the secondary peaks): per image a dict with rows (slot of each
+    row), theta, desc (capacity n_kp * max_orient rows) and n_rows, a device
+    int64 tensor [n_images] with the row counts (read it to trim)."""
+    import torch
+    lib = load()
+    ims = _images(images)
+    n = len(images)
+    P = params.c()
+    dev = images[0].device
+    if workspace is None:
+        workspace = torch.empty(max(describe_multi_workspace_size(images, params), 256),
+                                dtype=torch.uint8, device=dev)
+    if out is None:
+        caps = [int(k["x"].numel()) * max_orient for k in kps]
+        out = {"rows": [torch.empty(c, dtype=torch.int32, device=dev) for c in caps],
+               "theta": [torch.empty(c, dtype=torch.float32, device=dev) for c in caps],
+               "desc": [torch.empty((c, DESC_DIM), dtype=torch.float32, device=dev) for c in caps],
+               "n_rows": torch.zeros(n, dtype=torch.int64, device=dev)}
+    ptr = lambda ts: (c_vp * n)(*[t.data_ptr() for t in ts])
+    _check("lpsift_describe_multi", lib.lpsift_describe_multi(
+        ims, n, _kps(kps), ctypes.byref(P), max_orient, peak_ratio, workspace.data_ptr(),
+        workspace.numel(), ptr(out["rows"]), ptr(out["theta"]), ptr(out["desc"]),
+        out["n_rows"].data_ptr(), _stream(stream)))
+    return out
 
 
 def score(images, kps, params: Params, weights, out=None, stream=None):

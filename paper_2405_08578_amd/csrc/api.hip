@@ -182,6 +182,40 @@ int lpsift_describe_selected(const lpsift_image* imgs, int32_t n, const lpsift_k
                            static_cast<hipStream_t>(stream));
 }
 
+size_t lpsift_describe_multi_workspace_size(const lpsift_image* imgs, int32_t n,
+                                            const lpsift_params* p)
+{
+    Geometry g;
+    if (make_geometry(p, &g) != LPSIFT_OK || check_images(imgs, n) != LPSIFT_OK) return 0;
+    return describe_multi_workspace_bytes(imgs, n, g);
+}
+
+int lpsift_describe_multi(const lpsift_image* imgs, int32_t n, const lpsift_keypoints* kps,
+                          const lpsift_params* p, int32_t max_orient, float peak_ratio,
+                          void* workspace, size_t ws_bytes, int32_t* const* rows,
+                          float* const* theta, float* const* desc, int64_t* n_rows, void* stream)
+{
+    Geometry g;
+    int st = make_geometry(p, &g);
+    if (st == LPSIFT_EINVAL) return st;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    if (max_orient < 1 || max_orient > 4 || !(peak_ratio > 0.0f) || !(peak_ratio <= 1.0f))
+        return LPSIFT_EINVAL;
+    if (!rows || !theta || !desc || !n_rows || !workspace) return LPSIFT_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!rows[i] || !theta[i] || !desc[i]) return LPSIFT_EINVAL;
+    if (reinterpret_cast<uintptr_t>(n_rows) & 7u) return LPSIFT_EINVAL;
+    const int stk = check_keypoints(imgs, n, kps, p);
+    if (stk != LPSIFT_OK) return stk;
+    if (st != LPSIFT_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    if (ws_bytes < describe_multi_workspace_bytes(imgs, n, g)) return LPSIFT_ECAPACITY;
+    const MultiSpec ms{max_orient, peak_ratio, rows, n_rows};
+    return launch_describe_multi(imgs, n, kps, g, workspace, ms, theta, desc,
+                                 static_cast<hipStream_t>(stream));
+}
+
 // normalised log2 window size per scale (feature 256 of the scorer)
 static void scale_features(const lpsift_params* p, float* out)
 {

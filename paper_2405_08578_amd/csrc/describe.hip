@@ -133,12 +133,19 @@ struct DescImg {
     const int32_t* sel;    // list mode: slots to describe, outputs compacted
     int64_t n_sel;
     int64_t n_kp;          // slots of the image
+    // multi-orientation variant
+    float* obuf;           // [n_kp][kMaxOrient] angles in turns
+    int32_t* count;        // [n_kp] orientations per slot
+    int64_t* offset;       // [n_kp] first output row of each slot
+    int32_t* rows;         // output: slot of every row
 };
 
 struct DescArgs {   // passed by value: keep well under 4 KB
     int32_t n_images;
     int32_t n_scales;
     int32_t list;          // 1: describe img[i].sel[0 .. n_sel) only
+    int32_t max_orient;    // multi-orientation variant: 1 .. kMaxOrient
+    float peak_ratio;      // and its secondary-peak threshold
     ScaleGeom geom[LPSIFT_MAX_SCALES];
     int32_t L[LPSIFT_MAX_SCALES];
     // first slot of scale s in image i
@@ -161,6 +168,7 @@ __host__ __device__ inline int64_t band_items(int x, int64_t nby, int64_t nbx)
 constexpr int kWaves = 4;          // keypoints per workgroup
 constexpr int kUnroll = 4;         // visits per lane per step
 constexpr int kBins = 128 + 36;    // descriptor bins, then orientation bins
+constexpr int kMaxOrient = 4;      // orientations per keypoint (multi-orientation variant)
 
 __device__ inline float wave_sum(float v)
 {
@@ -182,16 +190,183 @@ __device__ inline void vote(unsigned long long* h, float w, float scale)
     atomicAdd(h, (unsigned long long)(w * scale));
 }
 
+// Kernel modes: one orientation and its descriptor per keypoint; the
+// orientation pass of the multi-orientation variant (counts and angles per
+// slot); descriptors at the angles that pass stored, rows compacted.
+enum { kModeFull = 0, kModeOrient = 1, kModeGiven = 2 };
+
+// Smoothed 36-bin orientation histogram of one keypoint; lane k < 36 returns
+// bin k, other lanes -1. Ends with the votes visible to the whole wave.
+__device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, bool live, int kx,
+                                             int ky, const float2* field, int W, int H,
+                                             const ScaleGeom& G, const int32_t* tables)
+{
+    const int n = live ? G.n_orient : 0;
+    const int per = (n + 63) / 64;
+    const float scale = fixed_scale(n);
+    const int32_t* tab = tables + G.off_orient;
+    for (int it0 = 0; it0 < per; it0 += kUnroll) {
+        int dx[kUnroll], dy[kUnroll];
+        bool ok[kUnroll];
+        float2 ft[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = lane * per + it0 + u;
+            ok[u] = (it0 + u < per) && j < n;
+            const int32_t e = ok[u] ? tab[j] : 0;
+            dx[u] = (int)(int16_t)(e & 0xFFFF);
+            dy[u] = e >> 16;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int px = kx + dx[u], py = ky + dy[u];
+            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
+            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (ft[u].x == 0.0f) continue;
+            const float wt = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
+            const float t = ft[u].y * 36.0f;
+            const float k0f = floorf(t);
+            const float fr = t - k0f;
+            int k0 = (int)k0f;
+            if (k0 >= 36) k0 -= 36;
+            const int k1 = (k0 == 35) ? 0 : k0 + 1;
+            vote(ho + k0, (1.0f - fr) * wt, scale);
+            vote(ho + k1, fr * wt, scale);
+        }
+    }
+    __syncthreads();
+    const float inv = 1.0f / scale;
+    float sm = -1.0f;
+    if (lane < 36) {
+        const float h2m = (float)ho[(lane + 34) % 36] * inv, h1m = (float)ho[(lane + 35) % 36] * inv;
+        const float h0 = (float)ho[lane] * inv;
+        const float h1p = (float)ho[(lane + 1) % 36] * inv, h2p = (float)ho[(lane + 2) % 36] * inv;
+        sm = (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f;
+    }
+    return sm;
+}
+
+// Highest value over the wave with its lane (lowest lane on ties).
+__device__ inline void wave_argmax(float& v, int& k)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(v, off);
+        const int okk = __shfl_xor(k, off);
+        if (ov > v || (ov == v && okk < k)) {
+            v = ov;
+            k = okk;
+        }
+    }
+}
+
+// Peak angle in turns: bin k refined by the parabola through its neighbours.
+__device__ inline float peak_turns(float sm, int k, float h0)
+{
+    const float hm = __shfl(sm, (k + 35) % 36);
+    const float hp = __shfl(sm, (k + 1) % 36);
+    const float den = hm - 2.0f * h0 + hp;
+    const float off = (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
+    return ((float)k + off) / 36.0f;
+}
+
+// Descriptor of one keypoint at angle th_turns: votes into hist[0..128),
+// normalise, clip at 0.2, renormalise; lane l returns elements l and l + 64.
+__device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, bool live, int kx,
+                                            int ky, const float2* field, int W, int H,
+                                            const ScaleGeom& G, const int32_t* tables,
+                                            float th_turns, float& r0, float& r1)
+{
+    float sn, cs;
+    sincospif(2.0f * th_turns, &sn, &cs);
+    const float iw = G.inv_ws;
+    const int nd = live ? G.n_desc : 0;
+    const int perd = (nd + 63) / 64;
+    const float dscale = fixed_scale(nd);
+    const int32_t* tabd = tables + G.off_desc;
+    for (int it0 = 0; it0 < perd; it0 += kUnroll) {
+        int dx[kUnroll], dy[kUnroll];
+        bool ok[kUnroll];
+        float2 ft[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = lane * perd + it0 + u;
+            ok[u] = (it0 + u < perd) && j < nd;
+            const int32_t e = ok[u] ? tabd[j] : 0;
+            dx[u] = (int)(int16_t)(e & 0xFFFF);
+            dy[u] = e >> 16;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int px = kx + dx[u], py = ky + dy[u];
+            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
+            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (ft[u].x == 0.0f) continue;
+            // offset rotated by -theta, in subregion units
+            const float fdx = (float)dx[u], fdy = (float)dy[u];
+            const float uu = (cs * fdx + sn * fdy) * iw;
+            const float vv = (cs * fdy - sn * fdx) * iw;
+            if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
+            const float m = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
+            float rel = ft[u].y - th_turns;
+            rel -= floorf(rel);
+            const float t = rel * 8.0f;
+            const float o0f = floorf(t);
+            const float fo = t - o0f;
+            int o0 = (int)o0f;
+            if (o0 >= 8) o0 -= 8;
+            const int o1 = (o0 + 1) & 7;
+            const float cu = uu + 1.5f, cv = vv + 1.5f;
+            const float ix0f = floorf(cu), iy0f = floorf(cv);
+            const float fx = cu - ix0f, fy = cv - iy0f;
+            const int ix0 = (int)ix0f, iy0 = (int)iy0f;
+#pragma unroll
+            for (int jy = 0; jy < 2; ++jy) {
+                const int iy = iy0 + jy;
+                if (iy < 0 || iy > 3) continue;
+                const float wy = jy ? fy : 1.0f - fy;
+#pragma unroll
+                for (int jx = 0; jx < 2; ++jx) {
+                    const int ix = ix0 + jx;
+                    if (ix < 0 || ix > 3) continue;
+                    const float wxy = m * (jx ? fx : 1.0f - fx) * wy;
+                    unsigned long long* cell = hist + (iy * 4 + ix) * 8;
+                    vote(cell + o0, wxy * (1.0f - fo), dscale);
+                    vote(cell + o1, wxy * fo, dscale);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const float dinv = 1.0f / dscale;
+    float d0 = (float)hist[lane] * dinv, d1 = (float)hist[lane + 64] * dinv;
+    float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
+    d0 = fminf(d0 / nrm, 0.2f);
+    d1 = fminf(d1 / nrm, 0.2f);
+    nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
+    r0 = d0 / nrm;
+    r1 = d1 / nrm;
+}
+
+template <int kMode>
 __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const int32_t* tables)
 {
     __shared__ unsigned long long hist_all[kWaves][kBins];
+    __shared__ float th_sh[kWaves][kMaxOrient];
+    __shared__ int cnt_sh[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long* hist = hist_all[wave];
 
     bool live = false, has_out = false;
     int sc = 0, im = 0;
     int64_t slot = 0, out_at = 0;
-    if (a.list) {
+    if (kMode == kModeFull && a.list) {
         // list mode: entries of every image in turn, each list from its end
         // (largest slots, i.e. largest scale, first); output at the entry
         int64_t j = (int64_t)blockIdx.x * kWaves + wave;
@@ -243,156 +418,123 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     for (int b = lane; b < kBins; b += 64) hist[b] = 0ull;
     __syncthreads();
 
-    // ---- orientation histogram: 36 bins ----
-    unsigned long long* ho = hist + 128;
-    const int n = live ? G.n_orient : 0;
-    const int per = (n + 63) / 64;
-    const float scale = fixed_scale(n);
-    const int32_t* tab = tables + G.off_orient;
-    for (int it0 = 0; it0 < per; it0 += kUnroll) {
-        int dx[kUnroll], dy[kUnroll];
-        bool ok[kUnroll];
-        float2 ft[kUnroll];
+    if (kMode != kModeGiven) {
+        // ---- orientation: smoothing, argmax (lowest bin on ties), parabola ----
+        const float sm = orient_hist(hist + 128, lane, live, kx, ky, field, W, H, G, tables);
+        float bv = sm;
+        int bk = lane;
+        wave_argmax(bv, bk);
+        const float th_turns = peak_turns(sm, bk, bv);
+        if (kMode == kModeFull) {
+            if (live && lane == 0) I.theta[out_at] = th_turns * 6.283185307179586f;
+            // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
+            float r0, r1;
+            describe_at(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns, r0, r1);
+            if (live) {
+                float* out = I.desc + out_at * 128;
+                out[lane] = r0;
+                out[lane + 64] = r1;
+            } else if (has_out) {   // list entry naming no slot of the image
+                float* out = I.desc + out_at * 128;
+                out[lane] = 0.0f;
+                out[lane + 64] = 0.0f;
+                if (lane == 0) I.theta[out_at] = __builtin_nanf("");
+            }
+        } else {
+            // secondary peaks: strict local maxima other than the dominant bin
+            // with height >= peak_ratio x the maximum, highest first
+            const float smm = __shfl(sm, (lane + 35) % 36), smp = __shfl(sm, (lane + 1) % 36);
+            float cv = (lane < 36 && lane != bk && sm > smm && sm > smp && sm >= a.peak_ratio * bv)
+                           ? sm : -1.0f;
+            int cnt = 1;
+            if (live && lane == 0) I.obuf[slot * kMaxOrient] = th_turns;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int j = lane * per + it0 + u;
-            ok[u] = (it0 + u < per) && j < n;
-            const int32_t e = ok[u] ? tab[j] : 0;
-            dx[u] = (int)(int16_t)(e & 0xFFFF);
-            dy[u] = e >> 16;
+            for (int m = 1; m < kMaxOrient; ++m) {
+                if (m >= a.max_orient) break;
+                float v = cv;
+                int k = lane;
+                wave_argmax(v, k);
+                if (v < 0.0f) break;
+                const float t = peak_turns(sm, k, v);
+                if (live && lane == 0) I.obuf[slot * kMaxOrient + m] = t;
+                if (lane == k) cv = -1.0f;
+                ++cnt;
+            }
+            if (live && lane == 0) I.count[slot] = cnt;
         }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int px = kx + dx[u], py = ky + dy[u];
-            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
-            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            if (ft[u].x == 0.0f) continue;
-            const float wt = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
-            const float t = ft[u].y * 36.0f;
-            const float k0f = floorf(t);
-            const float fr = t - k0f;
-            int k0 = (int)k0f;
-            if (k0 >= 36) k0 -= 36;
-            const int k1 = (k0 == 35) ? 0 : k0 + 1;
-            vote(ho + k0, (1.0f - fr) * wt, scale);
-            vote(ho + k1, fr * wt, scale);
-        }
+        return;
     }
+
+    // ---- given orientations: one descriptor row per (slot, orientation) ----
+    const int cnt = live ? I.count[slot] : 0;
+    const int64_t row0 = live ? I.offset[slot] : 0;
+    if (lane < kMaxOrient) th_sh[wave][lane] = (live && lane < cnt) ? I.obuf[slot * kMaxOrient + lane] : 0.0f;
+    if (lane == 0) cnt_sh[wave] = cnt;
     __syncthreads();
-
-    // smoothing, argmax (lowest bin on ties), parabolic refinement
-    const float inv = 1.0f / scale;
-    float sm = -1.0f;
-    if (lane < 36) {
-        const float h2m = (float)ho[(lane + 34) % 36] * inv, h1m = (float)ho[(lane + 35) % 36] * inv;
-        const float h0 = (float)ho[lane] * inv;
-        const float h1p = (float)ho[(lane + 1) % 36] * inv, h2p = (float)ho[(lane + 2) % 36] * inv;
-        sm = (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f;
-    }
-    float bv = sm;
-    int bk = lane;
+    int passes = 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const float ov = __shfl_xor(bv, off);
-        const int okk = __shfl_xor(bk, off);
-        if (ov > bv || (ov == bv && okk < bk)) {
-            bv = ov;
-            bk = okk;
+    for (int w = 0; w < kWaves; ++w) passes = cnt_sh[w] > passes ? cnt_sh[w] : passes;
+    for (int m = 0; m < passes; ++m) {
+        if (m > 0) {
+            for (int b = lane; b < 128; b += 64) hist[b] = 0ull;
+            __syncthreads();
         }
-    }
-    const float hm = __shfl(sm, (bk + 35) % 36);
-    const float hp = __shfl(sm, (bk + 1) % 36);
-    const float den = hm - 2.0f * bv + hp;
-    const float offp = (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
-    const float th_turns = ((float)bk + offp) / 36.0f;
-    if (live && lane == 0) I.theta[out_at] = th_turns * 6.283185307179586f;
-
-    // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
-    float sn, cs;
-    sincospif(2.0f * th_turns, &sn, &cs);
-    const float iw = G.inv_ws;
-    const int nd = live ? G.n_desc : 0;
-    const int perd = (nd + 63) / 64;
-    const float dscale = fixed_scale(nd);
-    const int32_t* tabd = tables + G.off_desc;
-    for (int it0 = 0; it0 < perd; it0 += kUnroll) {
-        int dx[kUnroll], dy[kUnroll];
-        bool ok[kUnroll];
-        float2 ft[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int j = lane * perd + it0 + u;
-            ok[u] = (it0 + u < perd) && j < nd;
-            const int32_t e = ok[u] ? tabd[j] : 0;
-            dx[u] = (int)(int16_t)(e & 0xFFFF);
-            dy[u] = e >> 16;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int px = kx + dx[u], py = ky + dy[u];
-            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
-            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            if (ft[u].x == 0.0f) continue;
-            // offset rotated by -theta0, in subregion units
-            const float fdx = (float)dx[u], fdy = (float)dy[u];
-            const float uu = (cs * fdx + sn * fdy) * iw;
-            const float vv = (cs * fdy - sn * fdx) * iw;
-            if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
-            const float m = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
-            float rel = ft[u].y - th_turns;
-            rel -= floorf(rel);
-            const float t = rel * 8.0f;
-            const float o0f = floorf(t);
-            const float fo = t - o0f;
-            int o0 = (int)o0f;
-            if (o0 >= 8) o0 -= 8;
-            const int o1 = (o0 + 1) & 7;
-            const float cu = uu + 1.5f, cv = vv + 1.5f;
-            const float ix0f = floorf(cu), iy0f = floorf(cv);
-            const float fx = cu - ix0f, fy = cv - iy0f;
-            const int ix0 = (int)ix0f, iy0 = (int)iy0f;
-#pragma unroll
-            for (int jy = 0; jy < 2; ++jy) {
-                const int iy = iy0 + jy;
-                if (iy < 0 || iy > 3) continue;
-                const float wy = jy ? fy : 1.0f - fy;
-#pragma unroll
-                for (int jx = 0; jx < 2; ++jx) {
-                    const int ix = ix0 + jx;
-                    if (ix < 0 || ix > 3) continue;
-                    const float wxy = m * (jx ? fx : 1.0f - fx) * wy;
-                    unsigned long long* cell = hist + (iy * 4 + ix) * 8;
-                    vote(cell + o0, wxy * (1.0f - fo), dscale);
-                    vote(cell + o1, wxy * fo, dscale);
-                }
+        const bool act = live && m < cnt;
+        const float th = th_sh[wave][m];
+        float r0, r1;
+        describe_at(hist, lane, act, kx, ky, field, W, H, G, tables, th, r0, r1);
+        if (act) {
+            const int64_t row = row0 + m;
+            float* out = I.desc + row * 128;
+            out[lane] = r0;
+            out[lane + 64] = r1;
+            if (lane == 0) {
+                I.theta[row] = th * 6.283185307179586f;
+                I.rows[row] = (int32_t)slot;
             }
         }
+        __syncthreads();   // the next pass clears this pass's histogram
     }
-    __syncthreads();
+}
 
-    // normalise, clip at 0.2, normalise again
-    const float dinv = 1.0f / dscale;
-    float d0 = (float)hist[lane] * dinv, d1 = (float)hist[lane + 64] * dinv;
-    float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
-    d0 = fminf(d0 / nrm, 0.2f);
-    d1 = fminf(d1 / nrm, 0.2f);
-    nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
-    if (live) {
-        float* out = I.desc + out_at * 128;
-        out[lane] = d0 / nrm;
-        out[lane + 64] = d1 / nrm;
-    } else if (has_out) {   // list entry naming no slot of the image
-        float* out = I.desc + out_at * 128;
-        out[lane] = 0.0f;
-        out[lane + 64] = 0.0f;
-        if (lane == 0) I.theta[out_at] = __builtin_nanf("");
+// Exclusive prefix of the per-slot orientation counts of each image (one
+// 1024-thread workgroup per image): row offset of every slot and the total.
+struct ScanImg {
+    const int32_t* count;
+    int64_t* offset;
+    int64_t n;
+    int64_t* total;
+};
+struct ScanArgs {
+    int32_t n_images;
+    ScanImg img[kDescBatch];
+};
+
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void orient_scan_kernel(ScanArgs a)
+{
+    __shared__ int64_t part[kScanThreads];
+    const ScanImg& I = a.img[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t per = (I.n + kScanThreads - 1) / kScanThreads;
+    const int64_t b = t * per, e = (b + per < I.n) ? b + per : I.n;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += I.count[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {   // inclusive Hillis-Steele scan
+        const int64_t v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
     }
+    int64_t run = part[t] - s;
+    for (int64_t i = b; i < e; ++i) {
+        I.offset[i] = run;
+        run += I.count[i];
+    }
+    if (t == kScanThreads - 1) *I.total = part[t];
 }
 
 size_t field_offset(const Geometry& g)
@@ -410,9 +552,27 @@ size_t describe_workspace_bytes(const lpsift_image* imgs, int n, const Geometry&
     return b;
 }
 
-int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
-                    const Geometry& g, void* ws, float* const* theta, float* const* desc,
-                    const int32_t* const* sel, const int64_t* n_sel, hipStream_t stream)
+namespace {
+
+int64_t slots_of(const lpsift_image& im, const Geometry& g)
+{
+    int64_t n_kp = 0;
+    for (int s = 0; s < g.n_scales; ++s)
+        n_kp += 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
+    return n_kp;
+}
+
+// Per-image buffers of the multi-orientation variant, after the fields:
+// angles [n_kp][kMaxOrient] f32, counts [n_kp] i32, row offsets [n_kp] i64.
+size_t multi_bytes(int64_t n_kp)
+{
+    return align_up((size_t)n_kp * kMaxOrient * 4, 256) + align_up((size_t)n_kp * 4, 256) +
+           align_up((size_t)n_kp * 8, 256);
+}
+
+int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, const Geometry& g,
+                 void* ws, float* const* theta, float* const* desc, const int32_t* const* sel,
+                 const int64_t* n_sel, const MultiSpec* ms, hipStream_t stream)
 {
     char* base = static_cast<char*>(ws);
     int32_t* tables = reinterpret_cast<int32_t*>(base);
@@ -430,6 +590,7 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
     if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
     size_t foff = field_offset(g);
+    size_t moff = describe_workspace_bytes(imgs, n, g);   // multi buffers follow the fields
     for (int b0 = 0, nb = 0; b0 < n; b0 += nb) {
         // images per launch pair (field + describe): at most kDescBatch, and
         // gradient fields of at most kFieldGroupBytes together so that they
@@ -444,9 +605,11 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
         }
         FieldArgs fa{};
         DescArgs da{};
+        ScanArgs sa{};
         fa.n_images = nb;
         da.n_images = nb;
         da.n_scales = g.n_scales;
+        sa.n_images = nb;
         int maxw = 0, maxh = 0;
         for (int i = 0; i < nb; ++i) {
             const lpsift_image& im = imgs[b0 + i];
@@ -456,11 +619,21 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
             maxw = im.width > maxw ? im.width : maxw;
             maxh = im.height > maxh ? im.height : maxh;
             const lpsift_keypoints& kp = kps[b0 + i];
-            int64_t n_kp = 0;
-            for (int s = 0; s < g.n_scales; ++s)
-                n_kp += 2 * n_windows(im.height, g.L[s]) * n_windows(im.width, g.L[s]);
+            const int64_t n_kp = slots_of(im, g);
             da.img[i] = DescImg{field, im.height, im.width, kp.x, kp.y, theta[b0 + i], desc[b0 + i],
-                                sel ? sel[b0 + i] : nullptr, sel ? n_sel[b0 + i] : 0, n_kp};
+                                sel ? sel[b0 + i] : nullptr, sel ? n_sel[b0 + i] : 0, n_kp,
+                                nullptr, nullptr, nullptr, nullptr};
+            if (ms) {
+                char* m = base + moff;
+                da.img[i].obuf = reinterpret_cast<float*>(m);
+                m += align_up((size_t)n_kp * kMaxOrient * 4, 256);
+                da.img[i].count = reinterpret_cast<int32_t*>(m);
+                m += align_up((size_t)n_kp * 4, 256);
+                da.img[i].offset = reinterpret_cast<int64_t*>(m);
+                da.img[i].rows = ms->rows[b0 + i];
+                moff += multi_bytes(n_kp);
+                sa.img[i] = ScanImg{da.img[i].count, da.img[i].offset, n_kp, ms->n_rows + b0 + i};
+            }
         }
         {
             TimedScope ts(LPSIFT_KERNEL_GRADIENT, stream);
@@ -470,6 +643,8 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
         da.list = sel ? 1 : 0;
+        da.max_orient = ms ? ms->max_orient : 1;
+        da.peak_ratio = ms ? ms->peak_ratio : 1.0f;
         // per-XCD band lists; the grid covers the longest one
         int64_t longest = 0;
         for (int s = 0; s < g.n_scales; ++s) {
@@ -492,25 +667,63 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
                                         n_windows(imgs[b0 + i].width, g.L[s]));
             longest = items > longest ? items : longest;
         }
+        const dim3 grid((unsigned)(((longest + kWaves - 1) / kWaves) * kXcds));
         if (sel) {
             int64_t entries = 0;
             for (int i = 0; i < nb; ++i) entries += n_sel[b0 + i];
             if (entries > 0) {
                 TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
-                hipLaunchKernelGGL(orient_describe_kernel,
+                hipLaunchKernelGGL(orient_describe_kernel<kModeFull>,
                                    dim3((unsigned)((entries + kWaves - 1) / kWaves)),
                                    dim3(64 * kWaves), 0, stream, da, tables);
                 if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
             }
+        } else if (ms) {
+            {
+                TimedScope ts(LPSIFT_KERNEL_ORIENT_MULTI, stream);
+                if (longest > 0)
+                    hipLaunchKernelGGL(orient_describe_kernel<kModeOrient>, grid, dim3(64 * kWaves),
+                                       0, stream, da, tables);
+                hipLaunchKernelGGL(orient_scan_kernel, dim3(nb), dim3(kScanThreads), 0, stream, sa);
+                if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+            }
+            if (longest > 0) {
+                TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
+                hipLaunchKernelGGL(orient_describe_kernel<kModeGiven>, grid, dim3(64 * kWaves), 0,
+                                   stream, da, tables);
+                if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+            }
         } else if (longest > 0) {
-            const int64_t per_xcd = (longest + kWaves - 1) / kWaves;
             TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
-            hipLaunchKernelGGL(orient_describe_kernel, dim3((unsigned)(per_xcd * kXcds)),
-                               dim3(64 * kWaves), 0, stream, da, tables);
+            hipLaunchKernelGGL(orient_describe_kernel<kModeFull>, grid, dim3(64 * kWaves), 0,
+                               stream, da, tables);
             if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
         }
     }
     return LPSIFT_OK;
+}
+
+}  // namespace
+
+int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
+                    const Geometry& g, void* ws, float* const* theta, float* const* desc,
+                    const int32_t* const* sel, const int64_t* n_sel, hipStream_t stream)
+{
+    return run_describe(imgs, n, kps, g, ws, theta, desc, sel, n_sel, nullptr, stream);
+}
+
+size_t describe_multi_workspace_bytes(const lpsift_image* imgs, int n, const Geometry& g)
+{
+    size_t b = describe_workspace_bytes(imgs, n, g);
+    for (int i = 0; i < n; ++i) b += multi_bytes(slots_of(imgs[i], g));
+    return b;
+}
+
+int launch_describe_multi(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
+                          const Geometry& g, void* ws, const MultiSpec& ms, float* const* theta,
+                          float* const* desc, hipStream_t stream)
+{
+    return run_describe(imgs, n, kps, g, ws, theta, desc, nullptr, nullptr, &ms, stream);
 }
 
 }  // namespace lpsift

@@ -90,6 +90,20 @@ int launch_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps
                     const Geometry& g, void* ws, float* const* theta, float* const* desc,
                     const int32_t* const* sel, const int64_t* n_sel, hipStream_t s);
 
+// Multi-orientation variant: up to max_orient orientations per slot
+// (secondary peaks >= peak_ratio x the highest), one descriptor row each,
+// rows compacted in slot order; n_rows: device int64 [n].
+struct MultiSpec {
+    int32_t max_orient;
+    float peak_ratio;
+    int32_t* const* rows;
+    int64_t* n_rows;
+};
+size_t describe_multi_workspace_bytes(const lpsift_image* imgs, int n, const Geometry& g);
+int launch_describe_multi(const lpsift_image* imgs, int n, const lpsift_keypoints* kps,
+                          const Geometry& g, void* ws, const MultiSpec& ms, float* const* theta,
+                          float* const* desc, hipStream_t stream);
+
 struct MatchPlan {
     int chunks;          // candidate-range split
     int64_t chunk_len;   // candidates per chunk, a multiple of 32

@@ -73,3 +73,24 @@ def oracle_features_at(img, kp, Ls, idx=None, return_hist=True):
     th, hist = oracle.orientation(img, x, y, ws, return_hist=True)
     desc = oracle.describe(img, x, y, ws, th)
     return th, desc, hist
+
+
+def multi_ambiguous(h, peak_ratio=0.8, tol=1e-5):
+    """True when a decision of the secondary-orientation rule on the smoothed
+    histogram h is within `tol` (relative to its maximum) of its boundary: the
+    threshold, a strictness test or the order of two bins that can be peaks
+    (among them the dominant tie), or when the support is flat."""
+    m = h.max()
+    if m <= 0.0:
+        return True
+    best = int(np.argmax(h))
+    high = [k for k in range(36) if h[k] >= (peak_ratio - tol) * m]
+    for k in high:
+        if k == best:                # taken whatever its neighbours and the threshold
+            continue
+        if abs(h[k] - peak_ratio * m) < tol * m:
+            return True
+        if min(abs(h[k] - h[(k - 1) % 36]), abs(h[k] - h[(k + 1) % 36])) < tol * m:
+            return True
+    v = np.sort(h[high])
+    return bool(np.any(np.diff(v) < tol * m))

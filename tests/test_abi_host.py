@@ -313,3 +313,33 @@ def test_u8_entry_validation(lib):
     assert call(w=None) == E
     assert call(nbytes=lib.lpsift_match_u8_workspace_size(10, 10) - 1) == lp.LPSIFT_ECAPACITY
     assert call(nA=0, qA=None, out=None) == lp.LPSIFT_OK                   # no queries: no launch
+
+
+def test_describe_multi_validation(lib):
+    P = lp.Params([16, 32]).c()
+    im = lp.lpsift_image()
+    im.data, im.height, im.width, im.pitch = 1 << 20, 64, 64, 64
+    ims = (lp.lpsift_image * 1)(im)
+    n_kp = lp.num_keypoints(64, 64, lp.Params([16, 32]))
+    kp = lp.lpsift_keypoints()
+    kp.x = kp.y = kp.scale = kp.type = kp.value = kp.contrast = 1 << 22
+    kp.capacity = n_kp
+    kps = (lp.lpsift_keypoints * 1)(kp)
+    need = lib.lpsift_describe_multi_workspace_size(ims, 1, ctypes.byref(P))
+    assert need > lib.lpsift_describe_workspace_size(ims, 1, ctypes.byref(P))
+    buf = (ctypes.c_void_p * 1)(1 << 23)
+    E = lp.LPSIFT_EINVAL
+
+    def call(mo=4, pr=0.8, ws=1 << 24, nbytes=need, rows=buf, n_rows=1 << 25):
+        return lib.lpsift_describe_multi(ims, 1, kps, ctypes.byref(P), mo, pr, ws, nbytes, rows,
+                                         buf, buf, n_rows, None)
+    assert call(mo=0) == E
+    assert call(mo=5) == E
+    assert call(pr=0.0) == E
+    assert call(pr=1.5) == E
+    assert call(pr=math.nan) == E
+    assert call(rows=None) == E
+    assert call(n_rows=None) == E
+    assert call(n_rows=(1 << 25) + 4) == E
+    assert call(ws=(1 << 24) + 128) == E
+    assert call(nbytes=need - 1) == lp.LPSIFT_ECAPACITY

@@ -10,6 +10,7 @@ import pytest
 import oracle
 import synth
 from oracle import multi_orient as MO
+from gpu_util import multi_ambiguous
 
 
 def bins(thetas):
@@ -87,21 +88,8 @@ def texture(n=160, seed=3):
     return synth.to_uint8(cv.tex, rng)
 
 
-def ambiguous(h, peak_ratio=0.8, tol=1e-9):
-    """A decision of the rule within `tol` (relative to the maximum) of its
-    boundary: the threshold, a strictness test or the order of two bins that
-    can be peaks (among them the dominant tie)."""
-    m = h.max()
-    if m <= 0.0:                     # flat support: no orientation at all
-        return True
-    high = [k for k in range(36) if h[k] >= (peak_ratio - tol) * m]
-    for k in high:
-        if abs(h[k] - peak_ratio * m) < tol * m:
-            return True
-        if min(abs(h[k] - h[(k - 1) % 36]), abs(h[k] - h[(k + 1) % 36])) < tol * m:
-            return True
-    v = np.sort(h[high])
-    return bool(np.any(np.diff(v) < tol * m))
+def ambiguous(h):
+    return multi_ambiguous(h, 0.8, tol=1e-9)
 
 
 def test_rot90_rotates_every_orientation():
