@@ -504,10 +504,16 @@ def main():
     for _ in range(max(1, args.warmup)):
         mo_call()
     _, ms_mo = timed(mo_call, args.steps, stream)
+    lp.timing_enable(True)
+    timed(mo_call, args.steps, stream)
+    kmo = kernel_table(lp.timing_read(), args.steps)
+    lp.timing_enable(False)
     nr = [int(v) for v in mo["n_rows"].cpu()]
     mm = lp.match([mo["desc"][0][:nr[0]]], [mo["desc"][1][:nr[1]]], stream=stream)[0]
     out["multi_orientation"] = {
         "describe_ms_both_images": round(ms_mo, 4),
+        "orientation_pass_ms": kmo["orient_multi"]["ms_per_step"],
+        "descriptor_pass_ms": kmo["describe"]["ms_per_step"],
         "single_orientation_describe_ms": round(kt["gradient"]["ms_per_step"] +
                                                 kt["describe"]["ms_per_step"], 4),
         "rows_per_keypoint": round(sum(nr) / (2 * n_kp), 4),

@@ -190,6 +190,25 @@ __device__ inline void vote(unsigned long long* h, float w, float scale)
     atomicAdd(h, (unsigned long long)(w * scale));
 }
 
+// Makes a wave's LDS writes visible to its own later reads. Enough where each
+// wave owns its LDS region (no other wave reads it), and lets the waves of a
+// workgroup run different numbers of passes.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool kWaveOnly>
+__device__ inline void hist_sync()
+{
+    if (kWaveOnly)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
 // Kernel modes: one orientation and its descriptor per keypoint; the
 // orientation pass of the multi-orientation variant (counts and angles per
 // slot); descriptors at the angles that pass stored, rows compacted.
@@ -275,6 +294,8 @@ __device__ inline float peak_turns(float sm, int k, float h0)
 
 // Descriptor of one keypoint at angle th_turns: votes into hist[0..128),
 // normalise, clip at 0.2, renormalise; lane l returns elements l and l + 64.
+// kWaveOnly: the wave synchronises alone (the caller's waves may diverge).
+template <bool kWaveOnly>
 __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, bool live, int kx,
                                             int ky, const float2* field, int W, int H,
                                             const ScaleGeom& G, const int32_t* tables,
@@ -343,7 +364,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
             }
         }
     }
-    __syncthreads();
+    hist_sync<kWaveOnly>();
     const float dinv = 1.0f / dscale;
     float d0 = (float)hist[lane] * dinv, d1 = (float)hist[lane + 64] * dinv;
     float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
@@ -358,8 +379,6 @@ template <int kMode>
 __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const int32_t* tables)
 {
     __shared__ unsigned long long hist_all[kWaves][kBins];
-    __shared__ float th_sh[kWaves][kMaxOrient];
-    __shared__ int cnt_sh[kWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long* hist = hist_all[wave];
 
@@ -416,7 +435,7 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     const int W = I.w, H = I.h;
 
     for (int b = lane; b < kBins; b += 64) hist[b] = 0ull;
-    __syncthreads();
+    hist_sync<kMode == kModeGiven>();
 
     if (kMode != kModeGiven) {
         // ---- orientation: smoothing, argmax (lowest bin on ties), parabola ----
@@ -429,7 +448,7 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
             if (live && lane == 0) I.theta[out_at] = th_turns * 6.283185307179586f;
             // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
             float r0, r1;
-            describe_at(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns, r0, r1);
+            describe_at<false>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns, r0, r1);
             if (live) {
                 float* out = I.desc + out_at * 128;
                 out[lane] = r0;
@@ -466,34 +485,26 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     }
 
     // ---- given orientations: one descriptor row per (slot, orientation) ----
+    // Each wave loops over its own slot's orientations and synchronises alone.
     const int cnt = live ? I.count[slot] : 0;
     const int64_t row0 = live ? I.offset[slot] : 0;
-    if (lane < kMaxOrient) th_sh[wave][lane] = (live && lane < cnt) ? I.obuf[slot * kMaxOrient + lane] : 0.0f;
-    if (lane == 0) cnt_sh[wave] = cnt;
-    __syncthreads();
-    int passes = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) passes = cnt_sh[w] > passes ? cnt_sh[w] : passes;
-    for (int m = 0; m < passes; ++m) {
+    for (int m = 0; m < cnt; ++m) {
         if (m > 0) {
             for (int b = lane; b < 128; b += 64) hist[b] = 0ull;
-            __syncthreads();
+            wave_sync();
         }
-        const bool act = live && m < cnt;
-        const float th = th_sh[wave][m];
+        const float th = I.obuf[slot * kMaxOrient + m];
         float r0, r1;
-        describe_at(hist, lane, act, kx, ky, field, W, H, G, tables, th, r0, r1);
-        if (act) {
-            const int64_t row = row0 + m;
-            float* out = I.desc + row * 128;
-            out[lane] = r0;
-            out[lane + 64] = r1;
-            if (lane == 0) {
-                I.theta[row] = th * 6.283185307179586f;
-                I.rows[row] = (int32_t)slot;
-            }
+        describe_at<true>(hist, lane, true, kx, ky, field, W, H, G, tables, th, r0, r1);
+        const int64_t row = row0 + m;
+        float* out = I.desc + row * 128;
+        out[lane] = r0;
+        out[lane + 64] = r1;
+        if (lane == 0) {
+            I.theta[row] = th * 6.283185307179586f;
+            I.rows[row] = (int32_t)slot;
         }
-        __syncthreads();   // the next pass clears this pass's histogram
+        wave_sync();   // the next pass clears this pass's histogram
     }
 }
 
