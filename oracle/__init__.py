@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline import this package; the product library never does, and the oracle
 never imports the product. The arithmetic lives in ``lpsift_oracle.c`` (plain
-C, double precision), ``ransac.py``, ``scorer.py``, ``quantized.py`` and
-``multi_orient.py`` (NumPy, double precision); this module only marshals
-arrays.
+C, double precision), ``ransac.py``, ``scorer.py``, ``quantized.py``,
+``multi_orient.py`` and ``warp.py`` (NumPy, double precision); this module
+only marshals arrays.
 
 Pins (what each function is checked against, in tests/test_oracle_*.py):
   detect       brute force on tiny images, Eq. 1 in exact rational arithmetic,
@@ -21,6 +21,10 @@ Pins (what each function is checked against, in tests/test_oracle_*.py):
   multi_orient secondary-peak rule on closed-form histograms (threshold,
                strictness, wrap, order, truncation, parabola), an image with
                orientations exactly {0, 90} degrees, rot90 equivariance
+  warp         identity / integer translations reproduce the image, a linear
+               ramp under affine and projective maps (closed form at the
+               preimage), the feathered mean of two constant images,
+               coverage counts, canvas bounds of known corners
   scorer       padded-slice patches, torch FP64 autograd and finite
                differences for the MLP gradient, Adam's closed-form first
                step and torch's Adam, brute-force sort for the prune
