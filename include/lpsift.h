@@ -60,7 +60,8 @@ enum lpsift_kernel {
     LPSIFT_KERNEL_MATCH_U8 = 13,       /* uint8 int8-matrix-core contraction with top-2 */
     LPSIFT_KERNEL_MATCH_U8_AUX = 14,   /* uint8 candidate terms and final merge */
     LPSIFT_KERNEL_ORIENT_MULTI = 15,   /* multi-orientation pass and row scan */
-    LPSIFT_KERNEL_COUNT = 16
+    LPSIFT_KERNEL_WARP = 16,           /* warp and blend into the mosaic canvas */
+    LPSIFT_KERNEL_COUNT = 17
 };
 
 /* Learned keypoint scorer: MLP 258 -> 64 -> 64 -> 1 (ReLU), parameters as one
@@ -390,6 +391,25 @@ int lpsift_ransac(const lpsift_keypoints* kpA, const lpsift_keypoints* kpB,
                   const lpsift_ransac_params* rp, void* workspace, size_t ws_bytes,
                   int32_t* const* slotA, int32_t* const* slotB, uint8_t* const* inlier,
                   double* H, int32_t* stats, void* stream);
+
+/* Warp and blend: the stitched canvas of registered images (Sec. 4, Fig. 2(f),
+ * Fig. 9; the paper fixes no blending rule, this one is feathering).
+ * G: host double [n_images][9], row-major, image k pixels -> reference pixels
+ * (the mosaic registration's transforms), each finite and invertible.
+ * Canvas pixel (u, v) is the reference point p = (u + x0, v + y0). Image k
+ * covers it when q = G_k^-1 p (divided by its third coordinate, in double)
+ * lies in [0, w_k - 1] x [0, h_k - 1]; it then contributes the bilinear sample
+ * of the image at q (neighbour index clamped at the last row / column) with
+ * weight min(q.x + 1, w_k - q.x, q.y + 1, h_k - q.y).
+ *  canvas  device float [out_h][out_w]: sum(weight x sample) / sum(weight),
+ *          sums in double over images in order, 0 where no image covers
+ *  count   device uint8 [out_h][out_w] (may be null): covering images
+ * n_images 1..16; out_w, out_h >= 0 with out_w * out_h < 2^31. Every canvas
+ * pixel is written. Errors: EINVAL (null pointer, bad sizes, a transform that
+ * is not finite or not invertible), EHIP. */
+int lpsift_warp_blend(const lpsift_image* imgs, int32_t n_images, const double* G, double x0,
+                      double y0, int32_t out_w, int32_t out_h, float* canvas, uint8_t* count,
+                      void* stream);
 
 /* Kernel timing, a profiling aid. lpsift_timing_enable(1) resets the sums
  * and makes every later launch of the kernels listed in lpsift_kernel bracket

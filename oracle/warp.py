@@ -96,12 +96,15 @@ def warp_blend(images: Sequence[np.ndarray], G: Sequence[np.ndarray], x0: float,
 
 def near_boundary(images: Sequence[np.ndarray], qs, margin: float = 1e-6) -> np.ndarray:
     """Pixels where some image's coverage decision is within `margin` pixels
-    of its boundary (the decision may flip under rounding)."""
+    of its boundary, the perimeter of [0, w - 1] x [0, h - 1] (the decision may
+    flip under rounding)."""
     near = None
     for img, (qx, qy) in zip(images, qs):
         h, w = np.asarray(img).shape
-        d = np.minimum(np.minimum(np.abs(qx), np.abs(qx - (w - 1))),
-                       np.minimum(np.abs(qy), np.abs(qy - (h - 1))))
-        n = d < margin
+        in_x = (qx > -margin) & (qx < w - 1 + margin)
+        in_y = (qy > -margin) & (qy < h - 1 + margin)
+        dx = np.minimum(np.abs(qx), np.abs(qx - (w - 1)))
+        dy = np.minimum(np.abs(qy), np.abs(qy - (h - 1)))
+        n = ((dx < margin) & in_y) | ((dy < margin) & in_x)
         near = n if near is None else (near | n)
     return near

@@ -63,7 +63,8 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_scorer_train_workspace_size", "lpsift_scorer_train_step", "lpsift_ransac_host",
            "lpsift_ransac_workspace_size", "lpsift_ransac", "lpsift_quantize_u8",
            "lpsift_match_u8_workspace_size", "lpsift_match_u8",
-           "lpsift_describe_multi_workspace_size", "lpsift_describe_multi")
+           "lpsift_describe_multi_workspace_size", "lpsift_describe_multi",
+           "lpsift_warp_blend")
 
 _lib = None
 
@@ -149,6 +150,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_describe_multi.argtypes = [P(lpsift_image), c_i32, P(lpsift_keypoints),
                                           P(lpsift_params), c_i32, c_f32, c_vp, ctypes.c_size_t,
                                           P(c_vp), P(c_vp), P(c_vp), c_vp, c_vp]
+    lib.lpsift_warp_blend.restype = ctypes.c_int
+    lib.lpsift_warp_blend.argtypes = [P(lpsift_image), c_i32, c_vp, c_f64, c_f64, c_i32, c_i32,
+                                      c_vp, c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -449,7 +453,7 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
 
 KERNELS = ("detect", "gradient", "describe", "match_norms", "match_fp32", "match_split",
            "match_rescore", "match_rematch", "match_lowp", "score", "prune", "train", "ransac",
-           "match_u8", "match_u8_aux", "orient_multi")
+           "match_u8", "match_u8_aux", "orient_multi", "warp")
 SCORER_PARAMS = 20801
 
 
@@ -654,6 +658,28 @@ def ransac_gpu(kpA, kpB, matches, uniforms, thresh: float = 3.0, selA=None, selB
         workspace.data_ptr(), workspace.numel(), ptr(slotA), ptr(slotB), ptr(inl), H.data_ptr(),
         stats.data_ptr(), _stream(stream)))
     return out
+
+
+def warp_blend(images, G, x0: float, y0: float, width: int, height: int, canvas=None,
+               count=None, with_count: bool = True, stream=None):
+    """Blend registered images (uint8 CUDA tensors) into a width x height
+    float canvas whose pixel (0, 0) is reference point (x0, y0); G: one 3x3
+    transform (image -> reference pixels) per image. Returns (canvas, count)."""
+    import numpy as np
+    import torch
+    n = len(images)
+    g = np.ascontiguousarray(np.stack([np.asarray(t, np.float64).reshape(9) for t in G]))
+    if g.shape != (n, 9):
+        raise ValueError("one 3x3 transform per image")
+    dev = images[0].device
+    if canvas is None:
+        canvas = torch.empty((height, width), dtype=torch.float32, device=dev)
+    if count is None and with_count:
+        count = torch.empty((height, width), dtype=torch.uint8, device=dev)
+    _check("lpsift_warp_blend", load().lpsift_warp_blend(
+        _images(images), n, g.ctypes.data, float(x0), float(y0), int(width), int(height),
+        canvas.data_ptr(), None if count is None else count.data_ptr(), _stream(stream)))
+    return canvas, count
 
 
 def ransac(xyA, xyB, samples, thresh: float = 3.0):

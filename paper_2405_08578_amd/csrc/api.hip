@@ -435,6 +435,85 @@ int lpsift_match_u8(const uint8_t* qA, int64_t nA, const uint8_t* qB, int64_t nB
                            static_cast<hipStream_t>(stream));
 }
 
+int lpsift_warp_blend(const lpsift_image* imgs, int32_t n, const double* G, double x0,
+                      double y0, int32_t out_w, int32_t out_h, float* canvas, uint8_t* count,
+                      void* stream)
+{
+    if (n < 1 || n > kWarpMax || !G) return LPSIFT_EINVAL;
+    const int sti = check_images(imgs, n);
+    if (sti != LPSIFT_OK) return sti;
+    if (out_w < 0 || out_h < 0 || (int64_t)out_w * out_h >= ((int64_t)1 << 31)) return LPSIFT_EINVAL;
+    if (!std::isfinite(x0) || !std::isfinite(y0)) return LPSIFT_EINVAL;
+    if ((int64_t)out_w * out_h > 0 && !canvas) return LPSIFT_EINVAL;
+    WarpArgs a{};
+    a.n = n;
+    a.W = out_w;
+    a.H = out_h;
+    a.x0 = x0;
+    a.y0 = y0;
+    a.canvas = canvas;
+    a.count = count;
+    for (int k = 0; k < n; ++k) {
+        const double* g = G + 9 * k;
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(g[i])) return LPSIFT_EINVAL;
+        // inverse by the adjugate
+        const double c00 = g[4] * g[8] - g[5] * g[7], c01 = g[5] * g[6] - g[3] * g[8],
+                     c02 = g[3] * g[7] - g[4] * g[6];
+        const double det = g[0] * c00 + g[1] * c01 + g[2] * c02;
+        double scale = 0.0;
+        for (int i = 0; i < 9; ++i) scale = std::fmax(scale, std::fabs(g[i]));
+        if (!(std::fabs(det) > 1e-12 * scale * scale * scale)) return LPSIFT_EINVAL;
+        const double id = 1.0 / det;
+        WarpImg& w = a.img[k];
+        w.hi[0] = c00 * id;
+        w.hi[1] = (g[2] * g[7] - g[1] * g[8]) * id;
+        w.hi[2] = (g[1] * g[5] - g[2] * g[4]) * id;
+        w.hi[3] = c01 * id;
+        w.hi[4] = (g[0] * g[8] - g[2] * g[6]) * id;
+        w.hi[5] = (g[2] * g[3] - g[0] * g[5]) * id;
+        w.hi[6] = c02 * id;
+        w.hi[7] = (g[1] * g[6] - g[0] * g[7]) * id;
+        w.hi[8] = (g[0] * g[4] - g[1] * g[3]) * id;
+        w.data = static_cast<const uint8_t*>(imgs[k].data);
+        w.pitch = imgs[k].pitch;
+        w.h = imgs[k].height;
+        w.w = imgs[k].width;
+        // canvas box of the mapped corners; the whole canvas when the map's
+        // denominator changes sign over the image (the image then reaches the
+        // line at infinity and its footprint is not bounded by the corners)
+        const double cx[4] = {0.0, (double)(w.w - 1), (double)(w.w - 1), 0.0};
+        const double cy[4] = {0.0, 0.0, (double)(w.h - 1), (double)(w.h - 1)};
+        double lo_x = INFINITY, hi_x = -INFINITY, lo_y = INFINITY, hi_y = -INFINITY;
+        int pos = 0, neg = 0;
+        for (int c = 0; c < 4; ++c) {
+            const double z = g[6] * cx[c] + g[7] * cy[c] + g[8];
+            pos += z > 0.0;
+            neg += z < 0.0;
+            const double X = (g[0] * cx[c] + g[1] * cy[c] + g[2]) / z;
+            const double Y = (g[3] * cx[c] + g[4] * cy[c] + g[5]) / z;
+            lo_x = std::fmin(lo_x, X);
+            hi_x = std::fmax(hi_x, X);
+            lo_y = std::fmin(lo_y, Y);
+            hi_y = std::fmax(hi_y, Y);
+        }
+        if (pos == 4 || neg == 4) {
+            const double bx0 = std::floor(lo_x - x0) - 1.0, bx1 = std::floor(hi_x - x0) + 2.0;
+            const double by0 = std::floor(lo_y - y0) - 1.0, by1 = std::floor(hi_y - y0) + 2.0;
+            w.bx0 = (int32_t)std::fmax(0.0, std::fmin((double)out_w, bx0));
+            w.bx1 = (int32_t)std::fmax(0.0, std::fmin((double)out_w, bx1));
+            w.by0 = (int32_t)std::fmax(0.0, std::fmin((double)out_h, by0));
+            w.by1 = (int32_t)std::fmax(0.0, std::fmin((double)out_h, by1));
+        } else {
+            w.bx0 = 0;
+            w.by0 = 0;
+            w.bx1 = out_w;
+            w.by1 = out_h;
+        }
+    }
+    return launch_warp_blend(a, static_cast<hipStream_t>(stream));
+}
+
 size_t lpsift_ransac_workspace_size(const int64_t* nq, int32_t n_pairs, int32_t n_iter)
 {
     if (!nq || n_pairs < 1 || n_iter < 0 || n_iter > (1 << 20)) return 0;

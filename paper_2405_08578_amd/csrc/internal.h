@@ -231,6 +231,25 @@ struct RansacBatch {
     const double* u;          // [n_iter][4][tries]
     RansacPair p[kRansacPairs];
 };
+// Warp and blend (warp.hip)
+constexpr int kWarpMax = 16;
+struct WarpImg {
+    const uint8_t* data;
+    int64_t pitch;
+    int32_t h, w;
+    double hi[9];                  // inverse transform: reference pixel -> image pixel
+    int32_t bx0, by0, bx1, by1;    // canvas box (half-open) outside which it covers nothing
+};
+struct WarpArgs {
+    int32_t n;
+    int32_t W, H;
+    double x0, y0;                 // canvas pixel (0, 0) = reference point (x0, y0)
+    float* canvas;
+    uint8_t* count;
+    WarpImg img[kWarpMax];
+};
+int launch_warp_blend(const WarpArgs& a, hipStream_t stream);
+
 // uint8 descriptors (match_u8.hip)
 int launch_quantize_u8(const float* desc, int64_t n, uint8_t* out, hipStream_t stream);
 size_t match_u8_workspace_bytes(int64_t nA, int64_t nB);

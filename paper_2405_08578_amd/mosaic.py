@@ -97,6 +97,23 @@ def register(n: int, T, W) -> Dict[str, object]:
             "reference": ref, "links": links}
 
 
+def canvas_bounds(shapes, G):
+    """Integer canvas of the registered images: (x0, y0, width, height) with
+    x0 the floor of the smallest mapped corner x, width reaching the floor of
+    the largest (same for y), so that canvas pixel (u, v) is reference point
+    (u + x0, v + y0). shapes: (h, w) per image; G: image -> reference."""
+    lo = np.array([np.inf, np.inf])
+    hi = -lo
+    for (h, w), g in zip(shapes, G):
+        corners = np.array([[0.0, 0.0], [w - 1.0, 0.0], [w - 1.0, h - 1.0], [0.0, h - 1.0]])
+        m = np.c_[corners, np.ones(4)] @ np.asarray(g, np.float64).T
+        xy = m[:, :2] / m[:, 2:]
+        lo = np.minimum(lo, xy.min(axis=0))
+        hi = np.maximum(hi, xy.max(axis=0))
+    x0, y0 = np.floor(lo)
+    return float(x0), float(y0), int(np.floor(hi[0]) - x0) + 1, int(np.floor(hi[1]) - y0) + 1
+
+
 def corner_error(G: np.ndarray, G_true: np.ndarray, w: int, h: int) -> float:
     """Largest distance between the image corners mapped by G and by G_true."""
     c = np.array([[0, 0, 1], [w - 1, 0, 1], [w - 1, h - 1, 1], [0, h - 1, 1]], np.float64)

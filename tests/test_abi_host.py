@@ -343,3 +343,48 @@ def test_describe_multi_validation(lib):
     assert call(n_rows=(1 << 25) + 4) == E
     assert call(ws=(1 << 24) + 128) == E
     assert call(nbytes=need - 1) == lp.LPSIFT_ECAPACITY
+
+
+def test_warp_blend_validation(lib):
+    import numpy as np
+    im = lp.lpsift_image()
+    im.data, im.height, im.width, im.pitch = 1 << 20, 30, 40, 40
+    ims = (lp.lpsift_image * 2)(im, im)
+    G = np.tile(np.eye(3).reshape(1, 9), (2, 1))
+    E = lp.LPSIFT_EINVAL
+    cv = ctypes.c_void_p(1 << 22)
+
+    def call(n=2, g=G, w=50, h=40, canvas=cv, x0=0.0):
+        g = np.ascontiguousarray(g, np.float64)
+        return lib.lpsift_warp_blend(ims, n, g.ctypes.data, x0, 0.0, w, h, canvas, None, None)
+    assert call(n=0) == E
+    assert call(n=17) == E
+    assert lib.lpsift_warp_blend(ims, 2, None, 0.0, 0.0, 5, 5, cv, None, None) == E
+    bad = G.copy()
+    bad[1, 4] = np.nan
+    assert call(g=bad) == E
+    sing = G.copy()
+    sing[0] = [1, 2, 0, 2, 4, 0, 0, 0, 1]           # rank 2
+    assert call(g=sing) == E
+    assert call(w=-1) == E
+    assert call(w=1 << 16, h=1 << 16) == E
+    assert call(canvas=None) == E
+    assert call(x0=math.inf) == E
+    assert call(w=0, h=0, canvas=None) == lp.LPSIFT_OK        # empty canvas: nothing launched
+
+
+def test_mosaic_canvas_bounds_matches_oracle():
+    import numpy as np
+    from paper_2405_08578_amd import mosaic
+    from oracle import warp as W
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        shapes = [(int(rng.integers(5, 300)), int(rng.integers(5, 300))) for _ in range(3)]
+        G = []
+        for _ in shapes:
+            g = np.eye(3)
+            g[:2, :2] += rng.normal(0, 0.2, (2, 2))
+            g[:2, 2] = rng.uniform(-500, 500, 2)
+            g[2, :2] = rng.normal(0, 1e-4, 2)
+            G.append(g)
+        assert mosaic.canvas_bounds(shapes, G) == W.canvas_bounds(shapes, G)
