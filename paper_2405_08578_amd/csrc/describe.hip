@@ -16,10 +16,11 @@
 //     accumulated in LDS as 64-bit fixed point with integer atomics:
 //     ds_add_u64 runs at close to full rate where ds_add_f32 does not, and
 //     integer sums do not depend on the order of the votes, so the result is
-//     bit-identical from run to run. The scale 2^(62 - b), with 2^b above
-//     (visits x 361) >= the total vote mass (|gradient| <= 255 sqrt 2, all
-//     interpolation weights <= 1), makes overflow impossible while resolving
-//     votes to ~2^-40 of the total. Orientation (36 bins, smoothing, argmax,
+//     bit-identical from run to run. A single vote is at most 255 sqrt 2 < 362
+//     (all interpolation weights <= 1), so at the fixed scale 2^23 it fits 32
+//     bits and converts with one v_cvt_u32_f32 (truncation, a quantum of
+//     2^-23 per vote); the 64-bit bins cannot overflow below 2^41 votes.
+//     Orientation (36 bins, smoothing, argmax,
 //     parabola), then the 128-bin descriptor, normalisation, clipping at 0.2
 //     and renormalisation happen in the same wave; the descriptor row is
 //     stored with two coalesced 256-byte writes.
@@ -177,17 +178,13 @@ __device__ inline float wave_sum(float v)
     return v;
 }
 
-// Fixed-point scale for at most `visits` votes of total mass <= visits * 361.
-__device__ inline float fixed_scale(int visits)
-{
-    const uint64_t bound = (uint64_t)visits * 361u + 1u;
-    const int bits = 64 - __clzll((long long)bound);
-    return exp2f((float)(62 - bits));
-}
+// Fixed-point scale of the votes (see the header); votes arrive pre-scaled.
+constexpr float kVoteScale = 8388608.0f;           // 2^23
+constexpr float kVoteInv = 1.0f / 8388608.0f;
 
-__device__ inline void vote(unsigned long long* h, float w, float scale)
+__device__ inline void vote(unsigned long long* h, float w_scaled)
 {
-    atomicAdd(h, (unsigned long long)(w * scale));
+    atomicAdd(h, (unsigned long long)(uint32_t)w_scaled);
 }
 
 // Makes a wave's LDS writes visible to its own later reads. Enough where each
@@ -222,7 +219,6 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
 {
     const int n = live ? G.n_orient : 0;
     const int per = (n + 63) / 64;
-    const float scale = fixed_scale(n);
     const int32_t* tab = tables + G.off_orient;
     for (int it0 = 0; it0 < per; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
@@ -245,19 +241,20 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ft[u].x == 0.0f) continue;
-            const float wt = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
+            const float wt = ft[u].x * kVoteScale *
+                             exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
             const float t = ft[u].y * 36.0f;
             const float k0f = floorf(t);
             const float fr = t - k0f;
             int k0 = (int)k0f;
             if (k0 >= 36) k0 -= 36;
             const int k1 = (k0 == 35) ? 0 : k0 + 1;
-            vote(ho + k0, (1.0f - fr) * wt, scale);
-            vote(ho + k1, fr * wt, scale);
+            vote(ho + k0, (1.0f - fr) * wt);
+            vote(ho + k1, fr * wt);
         }
     }
     __syncthreads();
-    const float inv = 1.0f / scale;
+    const float inv = kVoteInv;
     float sm = -1.0f;
     if (lane < 36) {
         const float h2m = (float)ho[(lane + 34) % 36] * inv, h1m = (float)ho[(lane + 35) % 36] * inv;
@@ -306,7 +303,6 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
     const float iw = G.inv_ws;
     const int nd = live ? G.n_desc : 0;
     const int perd = (nd + 63) / 64;
-    const float dscale = fixed_scale(nd);
     const int32_t* tabd = tables + G.off_desc;
     for (int it0 = 0; it0 < perd; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
@@ -334,7 +330,8 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
             const float uu = (cs * fdx + sn * fdy) * iw;
             const float vv = (cs * fdy - sn * fdx) * iw;
             if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
-            const float m = ft[u].x * exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
+            const float m = ft[u].x * kVoteScale *
+                            exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
             float rel = ft[u].y - th_turns;
             rel -= floorf(rel);
             const float t = rel * 8.0f;
@@ -358,14 +355,14 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
                     if (ix < 0 || ix > 3) continue;
                     const float wxy = m * (jx ? fx : 1.0f - fx) * wy;
                     unsigned long long* cell = hist + (iy * 4 + ix) * 8;
-                    vote(cell + o0, wxy * (1.0f - fo), dscale);
-                    vote(cell + o1, wxy * fo, dscale);
+                    vote(cell + o0, wxy * (1.0f - fo));
+                    vote(cell + o1, wxy * fo);
                 }
             }
         }
     }
     hist_sync<kWaveOnly>();
-    const float dinv = 1.0f / dscale;
+    const float dinv = kVoteInv;
     float d0 = (float)hist[lane] * dinv, d1 = (float)hist[lane + 64] * dinv;
     float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
     d0 = fminf(d0 / nrm, 0.2f);
@@ -407,18 +404,23 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
         }
     } else {
         // locate (scale, image, slot) of this wave's keypoint in its XCD's band list
+        // (32-bit arithmetic: window counts and slots of one image are < 2^31)
         const int xcd = blockIdx.x % kXcds;
         int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + wave;
         for (int so = 0; so < a.n_scales && !live; ++so) {
             const int s = a.n_scales - 1 - so;
+            const uint32_t L = (uint32_t)a.L[s];
             for (int i = 0; i < a.n_images; ++i) {
-                const int64_t nby = n_windows(a.img[i].h, a.L[s]), nbx = n_windows(a.img[i].w, a.L[s]);
-                const int64_t cnt = band_items(xcd, nby, nbx);
+                const uint32_t nby = ((uint32_t)a.img[i].h + L - 1u) / L;
+                const uint32_t nbx = ((uint32_t)a.img[i].w + L - 1u) / L;
+                const uint32_t r0 = (uint32_t)xcd * nby / kXcds;
+                const uint32_t r1 = (uint32_t)(xcd + 1) * nby / kXcds;
+                const int64_t cnt = 2 * (int64_t)(r1 - r0) * nbx;
                 if (j < cnt) {
                     live = true;
                     sc = s;
                     im = i;
-                    slot = a.slot_base[s][i] + 2 * ((xcd * nby) / kXcds) * nbx + j;
+                    slot = a.slot_base[s][i] + 2 * (int64_t)r0 * nbx + j;
                     break;
                 }
                 j -= cnt;
