@@ -300,7 +300,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 {
     float sn, cs;
     sincospif(2.0f * th_turns, &sn, &cs);
-    const float iw = G.inv_ws;
+    const float ca = cs * G.inv_ws, sa = sn * G.inv_ws;   // rotation by -theta, in cells
     const int nd = live ? G.n_desc : 0;
     const int perd = (nd + 63) / 64;
     const int32_t* tabd = tables + G.off_desc;
@@ -327,19 +327,17 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
             if (ft[u].x == 0.0f) continue;
             // offset rotated by -theta, in subregion units
             const float fdx = (float)dx[u], fdy = (float)dy[u];
-            const float uu = (cs * fdx + sn * fdy) * iw;
-            const float vv = (cs * fdy - sn * fdx) * iw;
+            const float uu = fmaf(ca, fdx, sa * fdy);
+            const float vv = fmaf(ca, fdy, -(sa * fdx));
             if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
             const float m = ft[u].x * kVoteScale *
                             exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
-            float rel = ft[u].y - th_turns;
-            rel -= floorf(rel);
-            const float t = rel * 8.0f;
-            const float o0f = floorf(t);
-            const float fo = t - o0f;
-            int o0 = (int)o0f;
-            if (o0 >= 8) o0 -= 8;
+            // direction bins o0 and o0 + 1 (mod 8) of the angle relative to theta
+            const float t = __builtin_amdgcn_fractf(ft[u].y - th_turns) * 8.0f;   // [0, 8)
+            const int o0 = (int)t;
+            const float fo = t - (float)o0;
             const int o1 = (o0 + 1) & 7;
+            const float m0 = m * (1.0f - fo), m1 = m * fo;
             const float cu = uu + 1.5f, cv = vv + 1.5f;
             const float ix0f = floorf(cu), iy0f = floorf(cv);
             const float fx = cu - ix0f, fy = cv - iy0f;
@@ -353,10 +351,10 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
                 for (int jx = 0; jx < 2; ++jx) {
                     const int ix = ix0 + jx;
                     if (ix < 0 || ix > 3) continue;
-                    const float wxy = m * (jx ? fx : 1.0f - fx) * wy;
+                    const float wxy = (jx ? fx : 1.0f - fx) * wy;
                     unsigned long long* cell = hist + (iy * 4 + ix) * 8;
-                    vote(cell + o0, wxy * (1.0f - fo));
-                    vote(cell + o1, wxy * fo);
+                    vote(cell + o0, m0 * wxy);
+                    vote(cell + o1, m1 * wxy);
                 }
             }
         }
