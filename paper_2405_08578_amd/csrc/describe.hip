@@ -11,8 +11,11 @@
 //     Each image pixel is visited by ~10 keypoint supports, so the atan2 and
 //     the square root are paid once per pixel instead of once per visit.
 //  3. orient_describe_kernel: one wavefront per keypoint, four per workgroup.
-//     Lane l walks the l-th contiguous 1/64 of the disc table, four visits at a
-//     time with all their loads issued before any is used. Votes are
+//     Lane l takes table entries l, l + 64, l + 128, ... (four at a time, all
+//     their loads issued before any is used), so one load instruction reads
+//     consecutive table entries and mostly neighbouring pixels of the field;
+//     lanes of even and odd index vote into two copies of the histogram, which
+//     halves the collisions of neighbouring pixels on one bin. Votes are
 //     accumulated in LDS as 64-bit fixed point with integer atomics:
 //     ds_add_u64 runs at close to full rate where ds_add_f32 does not, and
 //     integer sums do not depend on the order of the votes, so the result is
@@ -170,6 +173,10 @@ constexpr int kWaves = 4;          // keypoints per workgroup
 constexpr int kUnroll = 4;         // visits per lane per step
 constexpr int kBins = 128 + 36;    // descriptor bins, then orientation bins
 constexpr int kMaxOrient = 4;      // orientations per keypoint (multi-orientation variant)
+// Histogram copies per wave: lane l votes into copy l mod kCopies, so the
+// neighbouring pixels that neighbouring lanes visit rarely hit one address
+// at once; the copies are summed when read (integer sums: order-free).
+constexpr int kCopies = 2;
 
 __device__ inline float wave_sum(float v)
 {
@@ -220,13 +227,14 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
     const int n = live ? G.n_orient : 0;
     const int per = (n + 63) / 64;
     const int32_t* tab = tables + G.off_orient;
+    unsigned long long* hv = ho + (lane % kCopies) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < per; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
         float2 ft[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int j = lane * per + it0 + u;
+            const int j = (it0 + u) * 64 + lane;
             ok[u] = (it0 + u < per) && j < n;
             const int32_t e = ok[u] ? tab[j] : 0;
             dx[u] = (int)(int16_t)(e & 0xFFFF);
@@ -249,17 +257,23 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
             int k0 = (int)k0f;
             if (k0 >= 36) k0 -= 36;
             const int k1 = (k0 == 35) ? 0 : k0 + 1;
-            vote(ho + k0, (1.0f - fr) * wt);
-            vote(ho + k1, fr * wt);
+            vote(hv + k0, (1.0f - fr) * wt);
+            vote(hv + k1, fr * wt);
         }
     }
     __syncthreads();
     const float inv = kVoteInv;
     float sm = -1.0f;
     if (lane < 36) {
-        const float h2m = (float)ho[(lane + 34) % 36] * inv, h1m = (float)ho[(lane + 35) % 36] * inv;
-        const float h0 = (float)ho[lane] * inv;
-        const float h1p = (float)ho[(lane + 1) % 36] * inv, h2p = (float)ho[(lane + 2) % 36] * inv;
+        auto bin = [&](int k) {
+            unsigned long long v = 0ull;
+#pragma unroll
+            for (int c = 0; c < kCopies; ++c) v += ho[c * kBins + k];
+            return (float)v * inv;
+        };
+        const float h2m = bin((lane + 34) % 36), h1m = bin((lane + 35) % 36);
+        const float h0 = bin(lane);
+        const float h1p = bin((lane + 1) % 36), h2p = bin((lane + 2) % 36);
         sm = (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f;
     }
     return sm;
@@ -304,13 +318,14 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
     const int nd = live ? G.n_desc : 0;
     const int perd = (nd + 63) / 64;
     const int32_t* tabd = tables + G.off_desc;
+    unsigned long long* hv = hist + (lane % kCopies) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < perd; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
         float2 ft[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int j = lane * perd + it0 + u;
+            const int j = (it0 + u) * 64 + lane;
             ok[u] = (it0 + u < perd) && j < nd;
             const int32_t e = ok[u] ? tabd[j] : 0;
             dx[u] = (int)(int16_t)(e & 0xFFFF);
@@ -352,7 +367,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
                     const int ix = ix0 + jx;
                     if (ix < 0 || ix > 3) continue;
                     const float wxy = (jx ? fx : 1.0f - fx) * wy;
-                    unsigned long long* cell = hist + (iy * 4 + ix) * 8;
+                    unsigned long long* cell = hv + (iy * 4 + ix) * 8;
                     vote(cell + o0, m0 * wxy);
                     vote(cell + o1, m1 * wxy);
                 }
@@ -361,7 +376,13 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
     }
     hist_sync<kWaveOnly>();
     const float dinv = kVoteInv;
-    float d0 = (float)hist[lane] * dinv, d1 = (float)hist[lane + 64] * dinv;
+    unsigned long long s0 = 0ull, s1 = 0ull;
+#pragma unroll
+    for (int c = 0; c < kCopies; ++c) {
+        s0 += hist[c * kBins + lane];
+        s1 += hist[c * kBins + lane + 64];
+    }
+    float d0 = (float)s0 * dinv, d1 = (float)s1 * dinv;
     float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
     d0 = fminf(d0 / nrm, 0.2f);
     d1 = fminf(d1 / nrm, 0.2f);
@@ -373,7 +394,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 template <int kMode>
 __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const int32_t* tables)
 {
-    __shared__ unsigned long long hist_all[kWaves][kBins];
+    __shared__ unsigned long long hist_all[kWaves][kCopies * kBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long* hist = hist_all[wave];
 
@@ -434,7 +455,7 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     const float2* field = I.field;
     const int W = I.w, H = I.h;
 
-    for (int b = lane; b < kBins; b += 64) hist[b] = 0ull;
+    for (int b = lane; b < kCopies * kBins; b += 64) hist[b] = 0ull;
     hist_sync<kMode == kModeGiven>();
 
     if (kMode != kModeGiven) {
@@ -490,7 +511,9 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     const int64_t row0 = live ? I.offset[slot] : 0;
     for (int m = 0; m < cnt; ++m) {
         if (m > 0) {
-            for (int b = lane; b < 128; b += 64) hist[b] = 0ull;
+#pragma unroll
+            for (int c = 0; c < kCopies; ++c)
+                for (int b = lane; b < 128; b += 64) hist[c * kBins + b] = 0ull;
             wave_sync();
         }
         const float th = I.obuf[slot * kMaxOrient + m];
