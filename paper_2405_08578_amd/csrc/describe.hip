@@ -261,7 +261,7 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
             vote(hv + k1, fr * wt);
         }
     }
-    __syncthreads();
+    wave_sync();
     const float inv = kVoteInv;
     float sm = -1.0f;
     if (lane < 36) {
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
     const int W = I.w, H = I.h;
 
     for (int b = lane; b < kCopies * kBins; b += 64) hist[b] = 0ull;
-    hist_sync<kMode == kModeGiven>();
+    wave_sync();
 
     if (kMode != kModeGiven) {
         // ---- orientation: smoothing, argmax (lowest bin on ties), parabola ----
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const 
             if (live && lane == 0) I.theta[out_at] = th_turns * 6.283185307179586f;
             // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
             float r0, r1;
-            describe_at<false>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns, r0, r1);
+            describe_at<true>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns, r0, r1);
             if (live) {
                 float* out = I.desc + out_at * 128;
                 out[lane] = r0;
@@ -545,30 +545,56 @@ struct ScanArgs {
 };
 
 constexpr int kScanThreads = 1024;
+constexpr int kScanTile = 4 * kScanThreads;   // counts per pass: four per thread
 
+// Passes over tiles of 4,096 counts: thread t sums counts 4t .. 4t + 3 of the
+// tile (one 16-byte load), a shuffle scan within each wavefront and a scan of
+// the 16 wavefront totals give its exclusive prefix, and the tile total
+// carries into the next pass. Loads and stores are coalesced.
 __global__ __launch_bounds__(kScanThreads) void orient_scan_kernel(ScanArgs a)
 {
-    __shared__ int64_t part[kScanThreads];
+    __shared__ int64_t wsum[kScanThreads / 64];
     const ScanImg& I = a.img[blockIdx.x];
-    const int t = threadIdx.x;
-    const int64_t per = (I.n + kScanThreads - 1) / kScanThreads;
-    const int64_t b = t * per, e = (b + per < I.n) ? b + per : I.n;
-    int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += I.count[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {   // inclusive Hillis-Steele scan
-        const int64_t v = (t >= off) ? part[t - off] : 0;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < I.n; base += kScanTile) {
+        const int64_t i0 = base + 4 * t;
+        int c[4] = {0, 0, 0, 0};
+        if (i0 + 3 < I.n) {
+            const int4 v = *reinterpret_cast<const int4*>(I.count + i0);
+            c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k < I.n) c[k] = I.count[i0 + k];
+        }
+        const int sum = c[0] + c[1] + c[2] + c[3];
+        int x = sum;                                   // inclusive scan in the wavefront
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
         __syncthreads();
-        part[t] += v;
+        if (w == 0) {                                  // inclusive scan of the 16 totals
+            int64_t v = lane < kScanThreads / 64 ? wsum[lane] : 0;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const int64_t y = __shfl_up(v, off);
+                if (lane >= off) v += y;
+            }
+            if (lane < kScanThreads / 64) wsum[lane] = v;
+        }
         __syncthreads();
+        int64_t run = carry + (w > 0 ? wsum[w - 1] : 0) + (x - sum);
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < I.n) I.offset[i0 + k] = run;
+            run += c[k];
+        }
+        carry += wsum[kScanThreads / 64 - 1];
+        __syncthreads();                               // wsum is rewritten by the next pass
     }
-    int64_t run = part[t] - s;
-    for (int64_t i = b; i < e; ++i) {
-        I.offset[i] = run;
-        run += I.count[i];
-    }
-    if (t == kScanThreads - 1) *I.total = part[t];
+    if (t == 0) *I.total = carry;
 }
 
 size_t field_offset(const Geometry& g)
