@@ -471,6 +471,21 @@ def main():
                      "kernel": f"match_topk_f32_kernel, {flops / 1e9:.1f} GFLOP per launch, "
                                f"{k_ms:.4f} ms per launch (HIP events on its stream)"},
     }
+    # measured ceilings beside the published ones: a 1 GiB device copy and the
+    # matrix-core probes of the four precisions the matchers use
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms, _ = timed(lambda: dst.copy_(src), 5, stream)
+    out["measured_peaks"] = {
+        "hbm_copy_GBps": round(2 * src.numel() * 4 / (copy_ms * 1e-3) / 1e9, 1),
+        "mfma_fp32_tflops": round(lp.mfma_probe("fp32"), 1),
+        "mfma_bf16_tflops": round(lp.mfma_probe("bf16"), 1),
+        "mfma_fp8_tflops": round(lp.mfma_probe("fp8"), 1),
+        "mfma_int8_tops": round(lp.mfma_probe("int8"), 1),
+        "note": "rates reached by plain copies and register-only MFMA chains on this box; "
+                "roofline.peak stays the published figure"}
+    del src, dst
+
     # reduced-precision contractions on the same descriptors (side fields): the
     # split BF16x3 path is certified against the FP32 path, BF16 and FP8 are
     # approximate

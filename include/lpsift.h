@@ -424,6 +424,23 @@ int lpsift_warp_blend(const lpsift_image* imgs, int32_t n_images, const double* 
 int lpsift_timing_enable(int32_t on);
 int lpsift_timing_read(int32_t kernel, double* ms, int64_t* launches);
 
+/* Matrix-core throughput probes (a measurement aid, not part of the method):
+ * lpsift_probe runs, on `stream`, 2048 workgroups of four wavefronts, each
+ * wavefront `iters` rounds of four independent accumulator chains of one MFMA
+ * shape, and writes one checksum per wavefront to out (device float
+ * [lpsift_probe_out_size()]). lpsift_probe_ops gives the multiply-add count
+ * x 2 of such a call, so ops / elapsed time is the achieved rate.
+ * Errors: EINVAL (bad kind, iters outside 1 .. 2^24, null out), EHIP. */
+enum lpsift_probe_kind {
+    LPSIFT_PROBE_MFMA_F32 = 0,    /* v_mfma_f32_32x32x2_f32 */
+    LPSIFT_PROBE_MFMA_BF16 = 1,   /* v_mfma_f32_32x32x16_bf16 */
+    LPSIFT_PROBE_MFMA_FP8 = 2,    /* v_mfma_scale_f32_32x32x64_f8f6f4, E4M3 */
+    LPSIFT_PROBE_MFMA_I8 = 3      /* v_mfma_i32_32x32x32_i8 */
+};
+int64_t lpsift_probe_out_size(void);
+double lpsift_probe_ops(int32_t kind, int64_t iters);
+int lpsift_probe(int32_t kind, int64_t iters, float* out, void* stream);
+
 /* Homography between matched pairs by RANSAC (Sec. 2.5, Eq. 7), on the host in
  * FP64; no GPU involvement and no stream. Eq. 8's rigid transform is the special
  * case of a full homography (h33 = 1) fitted here.

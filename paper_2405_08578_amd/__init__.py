@@ -64,7 +64,7 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_ransac_workspace_size", "lpsift_ransac", "lpsift_quantize_u8",
            "lpsift_match_u8_workspace_size", "lpsift_match_u8",
            "lpsift_describe_multi_workspace_size", "lpsift_describe_multi",
-           "lpsift_warp_blend")
+           "lpsift_warp_blend", "lpsift_probe_out_size", "lpsift_probe_ops", "lpsift_probe")
 
 _lib = None
 
@@ -153,6 +153,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_warp_blend.restype = ctypes.c_int
     lib.lpsift_warp_blend.argtypes = [P(lpsift_image), c_i32, c_vp, c_f64, c_f64, c_i32, c_i32,
                                       c_vp, c_vp, c_vp]
+    lib.lpsift_probe_out_size.restype = c_i64
+    lib.lpsift_probe_out_size.argtypes = []
+    lib.lpsift_probe_ops.restype = c_f64
+    lib.lpsift_probe_ops.argtypes = [c_i32, c_i64]
+    lib.lpsift_probe.restype = ctypes.c_int
+    lib.lpsift_probe.argtypes = [c_i32, c_i64, c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
@@ -680,6 +686,30 @@ def warp_blend(images, G, x0: float, y0: float, width: int, height: int, canvas=
         _images(images), n, g.ctypes.data, float(x0), float(y0), int(width), int(height),
         canvas.data_ptr(), None if count is None else count.data_ptr(), _stream(stream)))
     return canvas, count
+
+
+PROBES = {"fp32": 0, "bf16": 1, "fp8": 2, "int8": 3}
+
+
+def mfma_probe(kind: str, iters: int = 4096, reps: int = 3, device=None) -> float:
+    """Achieved matrix-core rate (TFLOP/s or TOP/s) of the probe kernel of one
+    precision: the best of `reps` timed calls after one untimed call."""
+    import torch
+    lib = load()
+    k = PROBES[kind]
+    dev = device or torch.device("cuda:0")
+    out = torch.empty(int(lib.lpsift_probe_out_size()), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    _check("lpsift_probe", lib.lpsift_probe(k, iters, out.data_ptr(), stream.cuda_stream))
+    best = math.inf
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        _check("lpsift_probe", lib.lpsift_probe(k, iters, out.data_ptr(), stream.cuda_stream))
+        e[1].record(stream)
+        torch.cuda.synchronize(dev)
+        best = min(best, e[0].elapsed_time(e[1]))
+    return float(lib.lpsift_probe_ops(k, iters)) / (best * 1e-3) / 1e12
 
 
 def ransac(xyA, xyB, samples, thresh: float = 3.0):

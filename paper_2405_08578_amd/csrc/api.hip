@@ -435,6 +435,24 @@ int lpsift_match_u8(const uint8_t* qA, int64_t nA, const uint8_t* qB, int64_t nB
                            static_cast<hipStream_t>(stream));
 }
 
+int64_t lpsift_probe_out_size(void)
+{
+    return probe_out_floats();
+}
+
+double lpsift_probe_ops(int32_t kind, int64_t iters)
+{
+    if (kind < LPSIFT_PROBE_MFMA_F32 || kind > LPSIFT_PROBE_MFMA_I8 || iters < 1) return 0.0;
+    return probe_ops(kind, iters);
+}
+
+int lpsift_probe(int32_t kind, int64_t iters, float* out, void* stream)
+{
+    if (kind < LPSIFT_PROBE_MFMA_F32 || kind > LPSIFT_PROBE_MFMA_I8) return LPSIFT_EINVAL;
+    if (iters < 1 || iters > (1 << 24) || !out) return LPSIFT_EINVAL;
+    return launch_probe(kind, iters, out, static_cast<hipStream_t>(stream));
+}
+
 int lpsift_warp_blend(const lpsift_image* imgs, int32_t n, const double* G, double x0,
                       double y0, int32_t out_w, int32_t out_h, float* canvas, uint8_t* count,
                       void* stream)

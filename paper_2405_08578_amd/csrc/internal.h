@@ -231,6 +231,11 @@ struct RansacBatch {
     const double* u;          // [n_iter][4][tries]
     RansacPair p[kRansacPairs];
 };
+// Matrix-core probes (probe.hip)
+int64_t probe_out_floats();
+double probe_ops(int kind, int64_t iters);
+int launch_probe(int kind, int64_t iters, float* out, hipStream_t s);
+
 // Warp and blend (warp.hip)
 constexpr int kWarpMax = 16;
 struct WarpImg {

@@ -388,3 +388,20 @@ def test_mosaic_canvas_bounds_matches_oracle():
             g[2, :2] = rng.normal(0, 1e-4, 2)
             G.append(g)
         assert mosaic.canvas_bounds(shapes, G) == W.canvas_bounds(shapes, G)
+
+
+def test_probe_validation(lib):
+    out = ctypes.c_void_p(1 << 20)
+    assert lib.lpsift_probe_out_size() == 2048 * 4
+    assert lib.lpsift_probe(4, 10, out, None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_probe(-1, 10, out, None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_probe(0, 0, out, None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_probe(0, (1 << 24) + 1, out, None) == lp.LPSIFT_EINVAL
+    assert lib.lpsift_probe(0, 10, None, None) == lp.LPSIFT_EINVAL
+    # 2 x 32 x 32 x K multiply-adds per MFMA, 4 chains, one per wavefront
+    waves = 2048 * 4
+    assert lib.lpsift_probe_ops(0, 3) == 2 * 32 * 32 * 2 * 4 * 3 * waves
+    assert lib.lpsift_probe_ops(1, 3) == 2 * 32 * 32 * 16 * 4 * 3 * waves
+    assert lib.lpsift_probe_ops(2, 3) == 2 * 32 * 32 * 64 * 4 * 3 * waves
+    assert lib.lpsift_probe_ops(3, 3) == 2 * 32 * 32 * 32 * 4 * 3 * waves
+    assert lib.lpsift_probe_ops(7, 3) == 0.0
