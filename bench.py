@@ -206,6 +206,27 @@ def bench_tiles(args, dev):
         variants[name] = v
         del ap
         torch.cuda.empty_cache()
+    # exact uint8 variant of the step (quantise all 9 sets, integer match of
+    # every pair), graph-replayed
+    ap = AllPairs(imgs, P, u8=True)
+    ap.capture()
+    for _ in range(max(1, args.warmup)):
+        ap.replay()
+    wall, _ = timed(ap.replay, steps, stream)
+    lp.timing_enable(True)
+    ap.run()
+    kt = kernel_table(lp.timing_read(), 1)
+    lp.timing_enable(False)
+    same = sum(int((o["match"].cpu().numpy() == r).sum()) for o, r in zip(ap.out, ref_lists))
+    ops = sum(2.0 * n_kp[i] * n_kp[j] * 128 for i, j in ap.pairs)
+    k_ms = kt["match_u8"]["ms_per_step"]
+    variants["uint8_exact"] = {
+        "ms_per_step_graph": round(wall, 3), "pairs_per_s": round(36 * 1000.0 / wall, 3),
+        "kernels": kt, "contraction_int8_tops": round(ops / (k_ms * 1e-3) / 1e12, 1),
+        "matches": int(sum(int((o["match"] >= 0).sum().item()) for o in ap.out)),
+        "list_agreement_with_fp32": round(same / sum(len(m) for m in ref_lists), 6)}
+    del ap
+    torch.cuda.empty_cache()
     res["descriptors"] = int(sum(n_kp))
     res["match_gflop_per_step"] = round(flops / 1e9, 1)
     res["variants"] = variants

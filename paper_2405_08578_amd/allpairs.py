@@ -9,7 +9,10 @@ allocate nothing and never synchronise. The step can run eagerly or be
 captured once into a HIP graph (torch.cuda.CUDAGraph) and replayed: the
 launch sequence is fixed by the image shapes, and replays read the images from
 the same device buffers. Optionally the step ends with the batched GPU RANSAC
-of every pair (the pairwise homographies of the mosaic, Sec. 4).
+of every pair (the pairwise homographies of the mosaic, Sec. 4). With
+u8=True the match stage quantises every descriptor set to uint8 and runs the
+exact integer matcher on each pair (one workspace, reused pair after pair on
+the stream).
 """
 from __future__ import annotations
 
@@ -17,8 +20,8 @@ import math
 from typing import List, Optional, Tuple
 
 from . import (DESC_DIM, Params, describe, describe_workspace_size, detect, empty_keypoints,
-               load, match, match_params, match_workspace_size,
-               num_keypoints, ransac_gpu)
+               load, match, match_params, match_u8, match_u8_workspace_size,
+               match_workspace_size, num_keypoints, quantize_u8, ransac_gpu)
 
 
 def pair_list(n: int) -> List[Tuple[int, int]]:
@@ -28,7 +31,7 @@ def pair_list(n: int) -> List[Tuple[int, int]]:
 class AllPairs:
     def __init__(self, images, params: Params, precision: int = 0, b_chunks: int = 0,
                  ratio: float = 0.8, abs_thresh: float = math.inf, ransac_uniforms=None,
-                 ransac_thresh: float = 3.0):
+                 ransac_thresh: float = 3.0, u8: bool = False):
         """ransac_uniforms: optional float64 CUDA tensor [n_iter, 4, tries];
         when given, every step ends with the batched GPU RANSAC of all pairs
         (self.ransac: H [pairs, 9], stats [pairs, 3], slot and inlier lists)."""
@@ -52,9 +55,14 @@ class AllPairs:
         self.dws = torch.empty(max(describe_workspace_size(self.images, params), 256),
                                dtype=torch.uint8, device=dev)
         self.stats = torch.zeros(1, dtype=torch.int32, device=dev)
-        mp = match_params(ratio, abs_thresh, precision, b_chunks, None)
-        need = match_workspace_size([self.n_kp[i] for i, _ in self.pairs],
-                                    [self.n_kp[j] for _, j in self.pairs], mp)
+        self.u8 = u8
+        if u8:
+            self.q = [torch.empty((n, DESC_DIM), dtype=torch.uint8, device=dev) for n in self.n_kp]
+            need = max(match_u8_workspace_size(self.n_kp[i], self.n_kp[j]) for i, j in self.pairs)
+        else:
+            mp = match_params(ratio, abs_thresh, precision, b_chunks, None)
+            need = match_workspace_size([self.n_kp[i] for i, _ in self.pairs],
+                                        [self.n_kp[j] for _, j in self.pairs], mp)
         self.mws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
         self.out = [{"match": torch.empty(self.n_kp[i], dtype=torch.int32, device=dev),
                      "d1": torch.empty(self.n_kp[i], dtype=torch.float32, device=dev),
@@ -81,10 +89,17 @@ class AllPairs:
         detect(self.images, self.params, out=self.kps, stream=stream)
         describe(self.images, self.kps, self.params, workspace=self.dws, theta=self.theta,
                  desc=self.desc, stream=stream)
-        match([self.desc[i] for i, _ in self.pairs], [self.desc[j] for _, j in self.pairs],
-              ratio=self.ratio, abs_thresh=self.abs_thresh, precision=self.precision,
-              b_chunks=self.b_chunks, workspace=self.mws, out=self.out, stream=stream,
-              stats=self.stats)
+        if self.u8:
+            for d, q in zip(self.desc, self.q):
+                quantize_u8(d, out=q, stream=stream)
+            for (i, j), o in zip(self.pairs, self.out):
+                match_u8(self.q[i], self.q[j], ratio=self.ratio, abs_thresh=self.abs_thresh,
+                         workspace=self.mws, out=o, stream=stream)
+        else:
+            match([self.desc[i] for i, _ in self.pairs], [self.desc[j] for _, j in self.pairs],
+                  ratio=self.ratio, abs_thresh=self.abs_thresh, precision=self.precision,
+                  b_chunks=self.b_chunks, workspace=self.mws, out=self.out, stream=stream,
+                  stats=self.stats)
         if self.ransac_uniforms is not None:
             self.ransac = ransac_gpu([self.kps[i] for i, _ in self.pairs],
                                      [self.kps[j] for _, j in self.pairs],

@@ -149,3 +149,43 @@ def test_allpairs_full_tiles_sampled(gpu):
     check_oracle(tiles, ap, Ls, tile_k=2, pair_k=17, n_desc=400, n_query=512, seed=3)
     # overlapping tiles do match
     assert max(int((o["match"] >= 0).sum()) for o in ap.out) > 1000
+
+
+def test_allpairs_u8_graph_replays(gpu):
+    """The uint8 variant of the step (quantise every set, exact integer match
+    of every pair): lists bit-exact against the integer oracle on the step's
+    own uint8 descriptors, and graph replays bit-identical to the eager step."""
+    import torch
+    from oracle import quantized as Q
+    tiles = small_tiles(7)
+    Ls = [16, 32, 64]
+    imgs = [to_dev(t, gpu) for t in tiles.images]
+    ap = AllPairs(imgs, lp.Params(Ls), u8=True)
+    say("all pairs u8 eager")
+    ap.run()
+    torch.cuda.synchronize()
+    ref = snapshot(ap)
+    q = [t.cpu().numpy() for t in ap.q]
+    for k in (0, 5):
+        assert np.array_equal(q[k], Q.quantize_u8(ref["desc"][k]))
+    for pk in (0, 17, 35):
+        i, j = ap.pairs[pk]
+        o = Q.match_u8(q[i], q[j], 0.8)
+        g = ref["lists"][pk]
+        assert np.array_equal(g["match"], o["match"])
+        assert np.array_equal(g["d1"], o["d1"].astype(np.float32))
+        assert np.array_equal(g["d2"], o["d2"].astype(np.float32))
+    say("all pairs u8 capture")
+    ap.capture()
+    torch.cuda.synchronize()
+    for r in range(3):
+        scramble(ap)
+        for t in ap.q:
+            t.fill_(3)
+        torch.cuda.synchronize()
+        say("all pairs u8 replay", r)
+        ap.replay()
+        torch.cuda.synchronize()
+        got = snapshot(ap)
+        got["stats"] = ref["stats"]          # the uint8 step does not touch the counter
+        assert_same(got, ref)
