@@ -459,7 +459,13 @@ def main():
     # per pixel
     det_bytes = 2 * (h * w + n_kp * 15)
     grad_bytes = 2 * h * w * 9
-    rates = {"detect_GBps": round(det_bytes / (kt["detect"]["ms_per_step"] * 1e-3) / 1e9, 1),
+    # detect + describe against HBM with the algorithmic bytes of both: each
+    # image read once, per keypoint slot 16 B of keypoint, 4 B of theta and
+    # 512 B of descriptor written (the VALU bounds describe; see the notes)
+    dd_bytes = 2 * (h * w + n_kp * (16 + 4 + 512))
+    rates = {"detect_describe_algorithmic_GBps": round(dd_bytes / (dd_ms * 1e-3) / 1e9, 1),
+             "detect_describe_hbm_frac": round(dd_bytes / (dd_ms * 1e-3) / 1e9 / PEAK_HBM, 4),
+             "detect_GBps": round(det_bytes / (kt["detect"]["ms_per_step"] * 1e-3) / 1e9, 1),
              "gradient_GBps": round(grad_bytes / (kt["gradient"]["ms_per_step"] * 1e-3) / 1e9, 1),
              "describe_keypoints_per_s": round(2 * n_kp / (kt["describe"]["ms_per_step"] * 1e-3), 0)}
 
