@@ -153,3 +153,15 @@ def test_config1_sampled(gpu):
         idx = np.sort(rng.choice(len(kpn["x"]), 400, replace=False))
         check(img, kpn, rows, th, de, Ls, th1[i].cpu().numpy(), de1[i].cpu().numpy(), idx=idx,
               max_amb=0.01)
+
+
+def test_non_nested_windows(gpu):
+    """A window set that is not nested (the per-window detect kernel) through
+    the multi-orientation path."""
+    img = texture(300, 420, 9, 180)
+    Ls = [32, 40]
+    say("describe_multi non-nested", Ls)
+    kps, th1, de1, out = run(gpu, [img], Ls)
+    rows, th, de = host_rows(out, 0)
+    check(img, kp_numpy(kps[0]), rows, th, de, Ls, th1[0].cpu().numpy(), de1[0].cpu().numpy(),
+          max_amb=0.02)

@@ -121,3 +121,18 @@ def test_nine_tiles_sampled(gpu):
     v = rng.integers(0, h, 300000)
     compare(tiles.images, G, b, c, n, u, v, max_near=2e-3)
     assert (n >= 2).mean() > 0.2
+
+
+def test_without_count_buffer(gpu):
+    """count may be null: the canvas is the same as with it."""
+    import torch
+    imgs = [texture(90, 120, 21, 30), texture(100, 80, 22, 30)]
+    G = [np.eye(3), np.array([[0.9, 0.2, 60.0], [-0.2, 0.9, 30.0], [0, 0, 1.0]])]
+    b = mosaic.canvas_bounds([i.shape for i in imgs], G)
+    dev = [to_dev(i, gpu) for i in imgs]
+    say("warp without count")
+    c1, n1 = lp.warp_blend(dev, G, *b)
+    c2, n2 = lp.warp_blend(dev, G, *b, with_count=False)
+    torch.cuda.synchronize()
+    assert n2 is None
+    assert torch.equal(c1, c2)
