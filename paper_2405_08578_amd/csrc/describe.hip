@@ -263,20 +263,18 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
     }
     wave_sync();
     const float inv = kVoteInv;
-    float sm = -1.0f;
+    // lane k < 36 converts bin k once; its neighbours come by shuffles
+    float h0 = 0.0f;
     if (lane < 36) {
-        auto bin = [&](int k) {
-            unsigned long long v = 0ull;
+        unsigned long long v = 0ull;
 #pragma unroll
-            for (int c = 0; c < kCopies; ++c) v += ho[c * kBins + k];
-            return (float)v * inv;
-        };
-        const float h2m = bin((lane + 34) % 36), h1m = bin((lane + 35) % 36);
-        const float h0 = bin(lane);
-        const float h1p = bin((lane + 1) % 36), h2p = bin((lane + 2) % 36);
-        sm = (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f;
+        for (int c = 0; c < kCopies; ++c) v += ho[c * kBins + lane];
+        h0 = (float)v * inv;
     }
-    return sm;
+    const int l = lane < 36 ? lane : 0;
+    const float h2m = __shfl(h0, (l + 34) % 36), h1m = __shfl(h0, (l + 35) % 36);
+    const float h1p = __shfl(h0, (l + 1) % 36), h2p = __shfl(h0, (l + 2) % 36);
+    return lane < 36 ? (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f : -1.0f;
 }
 
 // Highest value over the wave with its lane (lowest lane on ties).
@@ -313,7 +311,8 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
                                             float th_turns, float& r0, float& r1)
 {
     float sn, cs;
-    sincospif(2.0f * th_turns, &sn, &cs);
+    sn = __builtin_amdgcn_sinf(th_turns);   // v_sin_f32 / v_cos_f32 take revolutions
+    cs = __builtin_amdgcn_cosf(th_turns);
     const float ca = cs * G.inv_ws, sa = sn * G.inv_ws;   // rotation by -theta, in cells
     const int nd = live ? G.n_desc : 0;
     const int perd = (nd + 63) / 64;
@@ -383,12 +382,12 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
         s1 += hist[c * kBins + lane + 64];
     }
     float d0 = (float)s0 * dinv, d1 = (float)s1 * dinv;
-    float nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
-    d0 = fminf(d0 / nrm, 0.2f);
-    d1 = fminf(d1 / nrm, 0.2f);
-    nrm = fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f);
-    r0 = d0 / nrm;
-    r1 = d1 / nrm;
+    float inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f));
+    d0 = fminf(d0 * inv, 0.2f);
+    d1 = fminf(d1 * inv, 0.2f);
+    inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f));
+    r0 = d0 * inv;
+    r1 = d1 * inv;
 }
 
 template <int kMode>
