@@ -391,7 +391,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 }
 
 template <int kMode>
-__global__ __launch_bounds__(256) void orient_describe_kernel(DescArgs a, const int32_t* tables)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void orient_describe_kernel(DescArgs a, const int32_t* tables)
 {
     __shared__ unsigned long long hist_all[kWaves][kCopies * kBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
