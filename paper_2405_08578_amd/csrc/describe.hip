@@ -149,6 +149,8 @@ struct DescArgs {   // passed by value: keep well under 4 KB
     int32_t n_scales;
     int32_t list;          // 1: describe img[i].sel[0 .. n_sel) only
     int32_t max_orient;    // multi-orientation variant: 1 .. kMaxOrient
+    int32_t first_scale;   // orient_describe_kernel: scales first_scale .. n_scales - 1
+    int32_t half_scales;   // orient_describe_half_kernel: scales 0 .. half_scales - 1
     float peak_ratio;      // and its secondary-peak threshold
     ScaleGeom geom[LPSIFT_MAX_SCALES];
     int32_t L[LPSIFT_MAX_SCALES];
@@ -173,6 +175,13 @@ constexpr int kWaves = 4;          // keypoints per workgroup
 constexpr int kUnroll = 4;         // visits per lane per step
 constexpr int kBins = 128 + 36;    // descriptor bins, then orientation bins
 constexpr int kMaxOrient = 4;      // orientations per keypoint (multi-orientation variant)
+// Scales whose descriptor disc has at most this many entries take the
+// half-wavefront kernel (L = 16 with the default geometry; measured: 2 % faster
+// than whole wavefronts there, slower once L = 32 is included).
+constexpr int kHalfMaxVisits = 700;
+// Histogram copies per half wavefront (even and odd lanes, as in the whole-
+// wavefront kernel).
+constexpr int kHalfCopies = 2;
 // Histogram copies per wave: lane l votes into copy l mod kCopies, so the
 // neighbouring pixels that neighbouring lanes visit rarely hit one address
 // at once; the copies are summed when read (integer sums: order-free).
@@ -220,21 +229,42 @@ enum { kModeFull = 0, kModeOrient = 1, kModeGiven = 2 };
 
 // Smoothed 36-bin orientation histogram of one keypoint; lane k < 36 returns
 // bin k, other lanes -1. Ends with the votes visible to the whole wave.
-__device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, bool live, int kx,
+// [1 4 6 4 1] / 16 smoothing of five neighbouring bins, written with explicit
+// FMAs so that every kernel rounds it the same way.
+__device__ inline float smooth5(float h2m, float h1m, float h0, float h1p, float h2p)
+{
+    float s = fmaf(4.0f, h1m, h2m);
+    s = fmaf(6.0f, h0, s);
+    s = fmaf(4.0f, h1p, s);
+    return (s + h2p) * 0.0625f;
+}
+
+// Parabolic offset of the peak at a bin of height h0 between hm and hp.
+__device__ inline float parabola_offset(float hm, float h0, float hp)
+{
+    const float den = fmaf(-2.0f, h0, hm) + hp;
+    return (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
+}
+
+// Orientation votes of one keypoint into ho[0..36) of each histogram copy;
+// its kStride lanes (sub = 0 .. kStride - 1) take table entries sub,
+// sub + kStride, ...
+template <int kStride, int kC = kCopies>
+__device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bool live, int kx,
                                              int ky, const float2* field, int W, int H,
                                              const ScaleGeom& G, const int32_t* tables)
 {
     const int n = live ? G.n_orient : 0;
-    const int per = (n + 63) / 64;
+    const int per = (n + kStride - 1) / kStride;
     const int32_t* tab = tables + G.off_orient;
-    unsigned long long* hv = ho + (lane % kCopies) * kBins;   // this lane's copy
+    unsigned long long* hv = ho + (sub % kC) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < per; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
         float2 ft[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int j = (it0 + u) * 64 + lane;
+            const int j = (it0 + u) * kStride + sub;
             ok[u] = (it0 + u < per) && j < n;
             const int32_t e = ok[u] ? tab[j] : 0;
             dx[u] = (int)(int16_t)(e & 0xFFFF);
@@ -261,6 +291,13 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
             vote(hv + k1, fr * wt);
         }
     }
+}
+
+__device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, bool live, int kx,
+                                             int ky, const float2* field, int W, int H,
+                                             const ScaleGeom& G, const int32_t* tables)
+{
+    orient_votes<64>(ho, lane, live, kx, ky, field, W, H, G, tables);
     wave_sync();
     const float inv = kVoteInv;
     // lane k < 36 converts bin k once; its neighbours come by shuffles
@@ -274,7 +311,7 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
     const int l = lane < 36 ? lane : 0;
     const float h2m = __shfl(h0, (l + 34) % 36), h1m = __shfl(h0, (l + 35) % 36);
     const float h1p = __shfl(h0, (l + 1) % 36), h2p = __shfl(h0, (l + 2) % 36);
-    return lane < 36 ? (h2m + 4.0f * h1m + 6.0f * h0 + 4.0f * h1p + h2p) / 16.0f : -1.0f;
+    return lane < 36 ? smooth5(h2m, h1m, h0, h1p, h2p) : -1.0f;
 }
 
 // Highest value over the wave with its lane (lowest lane on ties).
@@ -296,35 +333,35 @@ __device__ inline float peak_turns(float sm, int k, float h0)
 {
     const float hm = __shfl(sm, (k + 35) % 36);
     const float hp = __shfl(sm, (k + 1) % 36);
-    const float den = hm - 2.0f * h0 + hp;
-    const float off = (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
-    return ((float)k + off) / 36.0f;
+    return ((float)k + parabola_offset(hm, h0, hp)) / 36.0f;
 }
 
 // Descriptor of one keypoint at angle th_turns: votes into hist[0..128),
 // normalise, clip at 0.2, renormalise; lane l returns elements l and l + 64.
 // kWaveOnly: the wave synchronises alone (the caller's waves may diverge).
-template <bool kWaveOnly>
-__device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, bool live, int kx,
-                                            int ky, const float2* field, int W, int H,
-                                            const ScaleGeom& G, const int32_t* tables,
-                                            float th_turns, float& r0, float& r1)
+// Descriptor votes of one keypoint at angle th_turns into hist[0..128) of
+// each histogram copy; lanes as in orient_votes.
+template <int kStride, int kC = kCopies>
+__device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bool live, int kx,
+                                           int ky, const float2* field, int W, int H,
+                                           const ScaleGeom& G, const int32_t* tables,
+                                           float th_turns)
 {
     float sn, cs;
     sn = __builtin_amdgcn_sinf(th_turns);   // v_sin_f32 / v_cos_f32 take revolutions
     cs = __builtin_amdgcn_cosf(th_turns);
     const float ca = cs * G.inv_ws, sa = sn * G.inv_ws;   // rotation by -theta, in cells
     const int nd = live ? G.n_desc : 0;
-    const int perd = (nd + 63) / 64;
+    const int perd = (nd + kStride - 1) / kStride;
     const int32_t* tabd = tables + G.off_desc;
-    unsigned long long* hv = hist + (lane % kCopies) * kBins;   // this lane's copy
+    unsigned long long* hv = hist + (sub % kC) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < perd; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
         float2 ft[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int j = (it0 + u) * 64 + lane;
+            const int j = (it0 + u) * kStride + sub;
             ok[u] = (it0 + u < perd) && j < nd;
             const int32_t e = ok[u] ? tabd[j] : 0;
             dx[u] = (int)(int16_t)(e & 0xFFFF);
@@ -373,6 +410,15 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
             }
         }
     }
+}
+
+template <bool kWaveOnly>
+__device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, bool live, int kx,
+                                            int ky, const float2* field, int W, int H,
+                                            const ScaleGeom& G, const int32_t* tables,
+                                            float th_turns, float& r0, float& r1)
+{
+    desc_votes<64>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns);
     hist_sync<kWaveOnly>();
     const float dinv = kVoteInv;
     unsigned long long s0 = 0ull, s1 = 0ull;
@@ -382,10 +428,10 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
         s1 += hist[c * kBins + lane + 64];
     }
     float d0 = (float)s0 * dinv, d1 = (float)s1 * dinv;
-    float inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f));
+    float inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(fmaf(d0, d0, d1 * d1))), 1e-12f));
     d0 = fminf(d0 * inv, 0.2f);
     d1 = fminf(d1 * inv, 0.2f);
-    inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(d0 * d0 + d1 * d1)), 1e-12f));
+    inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(fmaf(d0, d0, d1 * d1))), 1e-12f));
     r0 = d0 * inv;
     r1 = d1 * inv;
 }
@@ -425,7 +471,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         // (32-bit arithmetic: window counts and slots of one image are < 2^31)
         const int xcd = blockIdx.x % kXcds;
         int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + wave;
-        for (int so = 0; so < a.n_scales && !live; ++so) {
+        for (int so = 0; so < a.n_scales - a.first_scale && !live; ++so) {
             const int s = a.n_scales - 1 - so;
             const uint32_t L = (uint32_t)a.L[s];
             for (int i = 0; i < a.n_images; ++i) {
@@ -527,6 +573,128 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             I.rows[row] = (int32_t)slot;
         }
         wave_sync();   // the next pass clears this pass's histogram
+    }
+}
+
+// Single-orientation path for the small scales (s < a.half_scales): each
+// 32-lane half of a wavefront describes its own keypoint (lanes take table
+// entries sub, sub + 32, ...), so the per-keypoint steps -- smoothing,
+// arg-max, rotation, normalisation -- serve two keypoints per instruction.
+// Same arithmetic as orient_describe_kernel<kModeFull>, except that the
+// normalisation sums add over 32 lanes in a different order.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void orient_describe_half_kernel(DescArgs a, const int32_t* tables)
+{
+    __shared__ unsigned long long hist_all[kWaves][2][kHalfCopies * kBins];
+    __shared__ float smv[kWaves][2][36];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int hf = lane >> 5, sub = lane & 31;
+    unsigned long long* hist = hist_all[wave][hf];
+    float* sv = smv[wave][hf];
+
+    // this half's keypoint in its XCD's band list of the small scales
+    bool live = false;
+    int sc = 0, im = 0;
+    int64_t slot = 0;
+    {
+        const int xcd = blockIdx.x % kXcds;
+        int64_t j = (int64_t)(blockIdx.x / kXcds) * (2 * kWaves) + 2 * wave + hf;
+        for (int so = 0; so < a.half_scales && !live; ++so) {
+            const int s = a.half_scales - 1 - so;
+            const uint32_t L = (uint32_t)a.L[s];
+            for (int i = 0; i < a.n_images; ++i) {
+                const uint32_t nby = ((uint32_t)a.img[i].h + L - 1u) / L;
+                const uint32_t nbx = ((uint32_t)a.img[i].w + L - 1u) / L;
+                const uint32_t r0 = (uint32_t)xcd * nby / kXcds;
+                const uint32_t r1 = (uint32_t)(xcd + 1) * nby / kXcds;
+                const int64_t cnt = 2 * (int64_t)(r1 - r0) * nbx;
+                if (j < cnt) {
+                    live = true;
+                    sc = s;
+                    im = i;
+                    slot = a.slot_base[s][i] + 2 * (int64_t)r0 * nbx + j;
+                    break;
+                }
+                j -= cnt;
+            }
+        }
+    }
+    if (!live) slot = 0;
+    const DescImg& I = a.img[im];
+    const ScaleGeom& G = a.geom[sc];
+    const int kx = I.x[slot], ky = I.y[slot];
+    const float2* field = I.field;
+    const int W = I.w, H = I.h;
+
+    for (int b = sub; b < kHalfCopies * kBins; b += 32) hist[b] = 0ull;
+    wave_sync();
+
+    // ---- orientation ----
+    orient_votes<32, kHalfCopies>(hist + 128, sub, live, kx, ky, field, W, H, G, tables);
+    wave_sync();
+    auto bin = [&](int k) {
+        unsigned long long v = 0ull;
+#pragma unroll
+        for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kBins + 128 + k];
+        return (float)v * kVoteInv;
+    };
+    auto smooth = [&](int k) {
+        return smooth5(bin((k + 34) % 36), bin((k + 35) % 36), bin(k), bin((k + 1) % 36),
+                       bin((k + 2) % 36));
+    };
+    // lane sub holds bin sub and, for sub < 4, bin 32 + sub
+    const float s1 = smooth(sub);
+    const float s2 = sub < 4 ? smooth(32 + sub) : -1.0f;
+    sv[sub] = s1;
+    if (sub < 4) sv[32 + sub] = s2;
+    float bv = s1;
+    int bk = sub;
+    if (s2 > bv) {            // bin 32 + sub above bin sub (ties keep the lower bin)
+        bv = s2;
+        bk = 32 + sub;
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(bv, off, 32);
+        const int okk = __shfl_xor(bk, off, 32);
+        if (ov > bv || (ov == bv && okk < bk)) {
+            bv = ov;
+            bk = okk;
+        }
+    }
+    wave_sync();
+    const float hm = sv[(bk + 35) % 36], hp = sv[(bk + 1) % 36];
+    const float th_turns = ((float)bk + parabola_offset(hm, bv, hp)) / 36.0f;
+    if (live && sub == 0) I.theta[slot] = th_turns * 6.283185307179586f;
+
+    // ---- descriptor: lane sub holds elements sub + 32 q ----
+    // The norms add (e, e + 64) pairs first, then the halves, then butterflies
+    // over 32 lanes: the summation tree of wave_sum in the whole-wave kernel,
+    // so both kernels give bit-identical descriptors.
+    desc_votes<32, kHalfCopies>(hist, sub, live, kx, ky, field, W, H, G, tables, th_turns);
+    wave_sync();
+    float d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        unsigned long long v = 0ull;
+#pragma unroll
+        for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kBins + sub + 32 * q];
+        d[q] = (float)v * kVoteInv;
+    }
+    auto half_norm = [&]() {
+        float ss = fmaf(d[0], d[0], d[2] * d[2]) + fmaf(d[1], d[1], d[3] * d[3]);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 32);
+        return __builtin_amdgcn_rcpf(fmaxf(sqrtf(ss), 1e-12f));
+    };
+    float inv = half_norm();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = fminf(d[q] * inv, 0.2f);
+    inv = half_norm();
+    if (live) {
+        float* out = I.desc + slot * 128;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[sub + 32 * q] = d[q] * inv;
     }
 }
 
@@ -753,9 +921,34 @@ int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, c
                 if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
             }
         } else if (longest > 0) {
+            // small scales on half wavefronts, the others on whole ones
+            int hs = 0;
+            while (hs < g.n_scales && g.s[hs].n_desc <= kHalfMaxVisits) ++hs;
+            int64_t half_longest = 0, full_longest = 0;
+            for (int x = 0; x < kXcds; ++x) {
+                int64_t ih = 0, ifu = 0;
+                for (int s = 0; s < g.n_scales; ++s)
+                    for (int i = 0; i < nb; ++i) {
+                        const int64_t it = band_items(x, n_windows(imgs[b0 + i].height, g.L[s]),
+                                                      n_windows(imgs[b0 + i].width, g.L[s]));
+                        (s < hs ? ih : ifu) += it;
+                    }
+                half_longest = ih > half_longest ? ih : half_longest;
+                full_longest = ifu > full_longest ? ifu : full_longest;
+            }
+            da.half_scales = hs;
+            da.first_scale = hs;
             TimedScope ts(LPSIFT_KERNEL_DESCRIBE, stream);
-            hipLaunchKernelGGL(orient_describe_kernel<kModeFull>, grid, dim3(64 * kWaves), 0,
-                               stream, da, tables);
+            if (full_longest > 0) {
+                const dim3 gf((unsigned)(((full_longest + kWaves - 1) / kWaves) * kXcds));
+                hipLaunchKernelGGL(orient_describe_kernel<kModeFull>, gf, dim3(64 * kWaves), 0,
+                                   stream, da, tables);
+            }
+            if (half_longest > 0) {
+                const dim3 gh((unsigned)(((half_longest + 2 * kWaves - 1) / (2 * kWaves)) * kXcds));
+                hipLaunchKernelGGL(orient_describe_half_kernel, gh, dim3(64 * kWaves), 0, stream, da,
+                                   tables);
+            }
             if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
         }
     }
