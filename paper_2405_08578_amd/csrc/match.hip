@@ -18,7 +18,13 @@
 //    registers while the current one is contracted; the candidate range is
 //    split into chunks so that the grid fills the chip.
 //  Each lane's top-2 of each chunk survives (4 candidates per query and
-//  chunk). The rescore kernel keeps the 4 best by contraction score,
+//  chunk). The accumulator starts at -|a|^2 / 2, so |b|^2 - 2 acc is the
+//  squared distance itself (non-negative up to rounding); a lane keeps 32-bit
+//  keys (its bits with the low 4 replaced by the accumulator row) with a min
+//  and a med3, which costs ~4 VALU instructions per score instead of ~9 for
+//  (score, index) compare-selects -- VALU and MFMA work do not overlap on
+//  this part. The 4-bit truncation moves a score by at most 15 units in the
+//  last place, below the FP32 contraction's own rounding. The rescore kernel keeps the 4 best by contraction score,
 //  recomputes their squared distances directly in FP32, takes the two
 //  smallest (lowest index on ties) and applies d1 < ratio * d2 in double.
 //
@@ -121,6 +127,15 @@ __global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X
 
 // ---------------------------------------------------------------- FP32 path --
 
+// Median of three signed integers (one VALU instruction; the compiler does
+// not form it from min/max).
+__device__ inline int smed3(int a, int b, int c)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // Branch-free insertion into a (score, index) top-2; on equal scores the
 // earlier (lower) index stays first because candidates arrive in index order.
 __device__ inline void top2_push(float s, int j, float& s1, int& j1, float& s2, int& j2)
@@ -155,8 +170,10 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     const int64_t cb = (int64_t)chunk * chunk_len;
     const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
 
-    // queries in registers: qa[i] = A[q0][h*64 + i], qb[i] = A[q1][h*64 + i]
+    // queries in registers: qa[i] = A[q0][h*64 + i], qb[i] = A[q1][h*64 + i];
+    // na, nb: |a|^2 of the two queries
     float qa[64], qb[64];
+    float na, nb;
     {
         const float4* pa = reinterpret_cast<const float4*>(A + q0 * 128 + h * 64);
         const float4* pb = reinterpret_cast<const float4*>(A + q1 * 128 + h * 64);
@@ -167,10 +184,25 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             qa[4 * i + 0] = va.x; qa[4 * i + 1] = va.y; qa[4 * i + 2] = va.z; qa[4 * i + 3] = va.w;
             qb[4 * i + 0] = vb.x; qb[4 * i + 1] = vb.y; qb[4 * i + 2] = vb.z; qb[4 * i + 3] = vb.w;
         }
+        float sa = 0.0f, sb = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            sa = fmaf(qa[i], qa[i], sa);
+            sb = fmaf(qb[i], qb[i], sb);
+        }
+        na = sa + __shfl_xor(sa, 32);
+        nb = sb + __shfl_xor(sb, 32);
     }
 
-    float sa1 = INFINITY, sa2 = INFINITY, sb1 = INFINITY, sb2 = INFINITY;
-    int ja1 = -1, ja2 = -1, jb1 = -1, jb2 = -1;
+    // Each lane keeps the top-2 of its candidates as 32-bit keys: the bits of
+    // the squared distance (|a|^2 enters through the accumulator's initial
+    // value -|a|^2 / 2) with the low 4 bits replaced by the accumulator row r,
+    // compared as signed integers (non-negative floats order like their bits;
+    // a distance rounded below zero sorts first). A key is kept with a min and
+    // a med3; the tile of each kept key is recovered once per tile by comparing
+    // the keys with their values before the tile.
+    int ka1 = 0x7FFFFFFF, ka2 = 0x7FFFFFFF, kb1 = 0x7FFFFFFF, kb2 = 0x7FFFFFFF;
+    int ta1 = -1, ta2 = -1, tb1 = -1, tb2 = -1;
 
     // prefetch: thread t moves float4 number t + 256 k (k < 4) of a 32 x 128 tile
     float4 pf[4];
@@ -201,8 +233,8 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
         floatx16 acc0, acc1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            acc0[r] = 0.0f;
-            acc1[r] = 0.0f;
+            acc0[r] = -0.5f * na;
+            acc1[r] = -0.5f * nb;
         }
         const float* trow = &tile[col * kRow + h * 64];
 #pragma unroll
@@ -217,27 +249,53 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, qa[4 * i4 + 3], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, qb[4 * i4 + 3], acc1, 0, 0, 0);
         }
-        // result row (candidate) of accumulator r in this lane: 8 (r/4) + 4 h + r % 4
+        // result row (candidate) of accumulator r in this lane: 8 (r/4) + 4 h + r % 4;
+        // squared distance |b|^2 - 2 acc = |a|^2 + |b|^2 - 2 a.b
+        const int pa1 = ka1, pa2 = ka2, pb1 = kb1, pb2 = kb2;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int cl = 8 * (r >> 2) + 4 * h + (r & 3);
-            const float nb = tnrm[cl];
-            const int j = (int)(t0 + cl);
-            top2_push(fmaf(-2.0f, acc0[r], nb), j, sa1, ja1, sa2, ja2);
-            top2_push(fmaf(-2.0f, acc1[r], nb), j, sb1, jb1, sb2, jb2);
+            const float nrm = tnrm[8 * (r >> 2) + 4 * h + (r & 3)];
+            const int xa = (__float_as_int(fmaf(-2.0f, acc0[r], nrm)) & -16) | r;
+            const int xb = (__float_as_int(fmaf(-2.0f, acc1[r], nrm)) & -16) | r;
+            ka2 = smed3(xa, ka1, ka2);
+            ka1 = min(xa, ka1);
+            kb2 = smed3(xb, kb1, kb2);
+            kb1 = min(xb, kb1);
         }
+        // a kept key equal to an earlier kept key is that one; else it is new
+        const int tt = (int)(t0 - cb);
+        ta2 = (ka2 == pa2) ? ta2 : ((ka2 == pa1) ? ta1 : tt);
+        ta1 = (ka1 == pa1) ? ta1 : tt;
+        tb2 = (kb2 == pb2) ? tb2 : ((kb2 == pb1) ? tb1 : tt);
+        tb1 = (kb1 == pb1) ? tb1 : tt;
     }
 
-    // candidates of padded rows carry score +inf and are never pushed
+    // key -> (candidate index, score); padded rows (score +inf) and empty
+    // slots give index -1
+    auto unpack = [&](int k, int t, int& j, float& sc) {
+        const int bits = k & -16;
+        const int r = k & 15;
+        const bool real = t >= 0 && bits < 0x7F800000;
+        j = real ? (int)cb + t + 8 * (r >> 2) + 4 * h + (r & 3) : -1;
+        sc = real ? __int_as_float(bits) : INFINITY;
+    };
     if (q0 >= 0) {
         const int64_t o = (i0 * chunks + chunk) * kKeep + 2 * h;
-        cidx[o] = ja1; cidx[o + 1] = ja2;
-        cscore[o] = sa1; cscore[o + 1] = sa2;
+        int j1, j2;
+        float s1, s2;
+        unpack(ka1, ta1, j1, s1);
+        unpack(ka2, ta2, j2, s2);
+        cidx[o] = j1; cidx[o + 1] = j2;
+        cscore[o] = s1; cscore[o + 1] = s2;
     }
     if (q1 >= 0) {
         const int64_t o = (i1 * chunks + chunk) * kKeep + 2 * h;
-        cidx[o] = jb1; cidx[o + 1] = jb2;
-        cscore[o] = sb1; cscore[o + 1] = sb2;
+        int j1, j2;
+        float s1, s2;
+        unpack(kb1, tb1, j1, s1);
+        unpack(kb2, tb2, j2, s2);
+        cidx[o] = j1; cidx[o + 1] = j2;
+        cscore[o] = s1; cscore[o + 1] = s2;
     }
 }
 
