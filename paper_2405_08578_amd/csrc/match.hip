@@ -167,8 +167,9 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     const int64_t i1 = i0 + 32;
     const int64_t q0 = (i0 < nq) ? (qlist ? qlist[i0] : i0) : -1;
     const int64_t q1 = (i1 < nq) ? (qlist ? qlist[i1] : i1) : -1;
-    const int64_t cb = (int64_t)chunk * chunk_len;
-    const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
+    // candidate rows cb .. ce - 1 (nB < 2^31: unsigned tile positions cannot wrap)
+    const uint32_t cb = (uint32_t)((int64_t)chunk * chunk_len);
+    const uint32_t ce = (uint32_t)(((int64_t)cb + chunk_len < nB) ? (int64_t)cb + chunk_len : nB);
 
     // queries in registers: qa[i] = A[q0][h*64 + i], qb[i] = A[q1][h*64 + i];
     // na, nb: |a|^2 of the two queries
@@ -204,21 +205,29 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     int ka1 = 0x7FFFFFFF, ka2 = 0x7FFFFFFF, kb1 = 0x7FFFFFFF, kb2 = 0x7FFFFFFF;
     int ta1 = -1, ta2 = -1, tb1 = -1, tb2 = -1;
 
-    // prefetch: thread t moves float4 number t + 256 k (k < 4) of a 32 x 128 tile
+    // prefetch: thread t moves float4 number t + 256 k (k < 4) of a 32 x 128
+    // tile (row (t + 256 k) / 32), threads t < 32 also the norm of row t; the
+    // base address is uniform, so a whole tile needs no per-lane address or
+    // bounds arithmetic
     float4 pf[4];
-    auto fetch = [&](int64_t t0) {
+    float pn = INFINITY;
+    auto fetch = [&](uint32_t t0) {
+        const float4* base = reinterpret_cast<const float4*>(B + (int64_t)t0 * 128);
+        if (ce - t0 >= (uint32_t)kCT) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int f = tid + 256 * k;
-            const int r = f >> 5, c4 = f & 31;
-            const int64_t j = t0 + r;
-            pf[k] = (j < ce) ? reinterpret_cast<const float4*>(B + j * 128)[c4]
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int k = 0; k < 4; ++k) pf[k] = base[tid + 256 * k];
+            if (tid < kCT) pn = nrmB[t0 + tid];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                pf[k] = ((uint32_t)((tid + 256 * k) >> 5) < ce - t0) ? base[tid + 256 * k]
+                                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (tid < kCT) pn = ((uint32_t)tid < ce - t0) ? nrmB[t0 + tid] : INFINITY;
         }
     };
     if (cb < ce) fetch(cb);
 
-    for (int64_t t0 = cb; t0 < ce; t0 += kCT) {
+    for (uint32_t t0 = cb; t0 < ce; t0 += kCT) {
         __syncthreads();   // the previous tile is no longer read
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -226,9 +235,9 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             const int r = f >> 5, c4 = f & 31;
             *reinterpret_cast<float4*>(&tile[r * kRow + c4 * 4]) = pf[k];
         }
-        if (tid < kCT) tnrm[tid] = (t0 + tid < ce) ? nrmB[t0 + tid] : INFINITY;
+        if (tid < kCT) tnrm[tid] = pn;
         __syncthreads();
-        if (t0 + kCT < ce) fetch(t0 + kCT);
+        if (ce - t0 > (uint32_t)kCT) fetch(t0 + kCT);
 
         floatx16 acc0, acc1;
 #pragma unroll
@@ -263,7 +272,7 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             kb1 = min(xb, kb1);
         }
         // a kept key equal to an earlier kept key is that one; else it is new
-        const int tt = (int)(t0 - cb);
+        const int tt = (int)(t0 - cb);   // chunk-relative tile start
         ta2 = (ka2 == pa2) ? ta2 : ((ka2 == pa1) ? ta1 : tt);
         ta1 = (ka1 == pa1) ? ta1 : tt;
         tb2 = (kb2 == pb2) ? tb2 : ((kb2 == pb1) ? tb1 : tt);
