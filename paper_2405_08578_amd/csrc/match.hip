@@ -127,12 +127,19 @@ __global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X
 
 // ---------------------------------------------------------------- FP32 path --
 
-// Median of three signed integers (one VALU instruction; the compiler does
-// not form it from min/max).
+// Medians of three integers (one VALU instruction each; the compiler does
+// not form them from min/max).
 __device__ inline int smed3(int a, int b, int c)
 {
     int r;
     asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ inline uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
 
@@ -617,9 +624,10 @@ __global__ __launch_bounds__(256, 1) void match_topk_lp_kernel(
                     const float sc = (P == 1) ? fmaf(-2.0f, acc[t][r], nb)
                                               : fmaf(qs2[t] * tsb[cl], acc[t][r], nb);
                     const uint32_t key = (__float_as_uint(sc) & ~idx_mask) | idx;
-                    // sorted insertion network (keys are unique): min / med3
-                    if (K == 3) k3[t] = max(k2[t], min(k3[t], max(k1[t], key)));
-                    k2[t] = max(k1[t], min(k2[t], key));
+                    // sorted insertion (k1 <= k2 <= k3, keys unique): the new
+                    // i-th smallest is key clamped to [k(i-1), k(i)]
+                    if (K == 3) k3[t] = umed3(key, k2[t], k3[t]);
+                    k2[t] = umed3(key, k1[t], k2[t]);
                     k1[t] = min(k1[t], key);
                 }
             }
