@@ -174,6 +174,11 @@ __host__ __device__ inline int64_t band_items(int x, int64_t nby, int64_t nbx)
 constexpr int kWaves = 4;          // keypoints per workgroup
 constexpr int kUnroll = 4;         // visits per lane per step
 constexpr int kBins = 128 + 36;    // descriptor bins, then orientation bins
+// Bins before the first histogram of a workgroup's LDS: a descriptor vote
+// addresses its four cells from one base at cell (iy0, ix0) >= (-1, -1),
+// which may lie up to 5 cells before the histogram (only in-range cells are
+// written).
+constexpr int kCellPad = 40;
 constexpr int kMaxOrient = 4;      // orientations per keypoint (multi-orientation variant)
 // Scales whose descriptor disc has at most this many entries take the
 // half-wavefront kernel (L = 16 with the default geometry; measured: 2 % faster
@@ -279,8 +284,10 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ft[u].x == 0.0f) continue;
+            // the exponent is above -7 for every geometry, far from the
+            // denormal range that exp2f guards against: v_exp_f32 alone
             const float wt = ft[u].x * kVoteScale *
-                             exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
+                             __builtin_amdgcn_exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
             const float t = ft[u].y * 36.0f;
             const float k0f = floorf(t);
             const float fr = t - k0f;
@@ -382,7 +389,7 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
             const float vv = fmaf(ca, fdy, -(sa * fdx));
             if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
             const float m = ft[u].x * kVoteScale *
-                            exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
+                            __builtin_amdgcn_exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
             // direction bins o0 and o0 + 1 (mod 8) of the angle relative to theta
             const float t = __builtin_amdgcn_fractf(ft[u].y - th_turns) * 8.0f;   // [0, 8)
             const int o0 = (int)t;
@@ -392,20 +399,20 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
             const float cu = uu + 1.5f, cv = vv + 1.5f;
             const float ix0f = floorf(cu), iy0f = floorf(cv);
             const float fx = cu - ix0f, fy = cv - iy0f;
-            const int ix0 = (int)ix0f, iy0 = (int)iy0f;
+            const int ix0 = (int)ix0f, iy0 = (int)iy0f;   // -1 .. 3
+            // bins o0 and o1 of the four cells at constant offsets from two bases
+            unsigned long long* b0 = hv + (iy0 * 4 + ix0) * 8 + o0;
+            unsigned long long* b1 = hv + (iy0 * 4 + ix0) * 8 + o1;
 #pragma unroll
             for (int jy = 0; jy < 2; ++jy) {
-                const int iy = iy0 + jy;
-                if (iy < 0 || iy > 3) continue;
+                if ((unsigned)(iy0 + jy) > 3u) continue;
                 const float wy = jy ? fy : 1.0f - fy;
 #pragma unroll
                 for (int jx = 0; jx < 2; ++jx) {
-                    const int ix = ix0 + jx;
-                    if (ix < 0 || ix > 3) continue;
+                    if ((unsigned)(ix0 + jx) > 3u) continue;
                     const float wxy = (jx ? fx : 1.0f - fx) * wy;
-                    unsigned long long* cell = hv + (iy * 4 + ix) * 8;
-                    vote(cell + o0, m0 * wxy);
-                    vote(cell + o1, m1 * wxy);
+                    vote(b0 + (jy * 4 + jx) * 8, m0 * wxy);
+                    vote(b1 + (jy * 4 + jx) * 8, m1 * wxy);
                 }
             }
         }
@@ -439,9 +446,9 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 template <int kMode>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void orient_describe_kernel(DescArgs a, const int32_t* tables)
 {
-    __shared__ unsigned long long hist_all[kWaves][kCopies * kBins];
+    __shared__ unsigned long long hist_mem[kCellPad + kWaves * kCopies * kBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long* hist = hist_all[wave];
+    unsigned long long* hist = hist_mem + kCellPad + wave * kCopies * kBins;
 
     bool live = false, has_out = false;
     int sc = 0, im = 0;
@@ -585,11 +592,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void orient_describe_half_kernel(DescArgs a, const int32_t* tables)
 {
-    __shared__ unsigned long long hist_all[kWaves][2][kHalfCopies * kBins];
+    __shared__ unsigned long long hist_mem[kCellPad + kWaves * 2 * kHalfCopies * kBins];
     __shared__ float smv[kWaves][2][36];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int hf = lane >> 5, sub = lane & 31;
-    unsigned long long* hist = hist_all[wave][hf];
+    unsigned long long* hist = hist_mem + kCellPad + (wave * 2 + hf) * kHalfCopies * kBins;
     float* sv = smv[wave][hf];
 
     // this half's keypoint in its XCD's band list of the small scales
