@@ -41,8 +41,11 @@
 // Split path (precision 3, exact): each FP32 value is split into two BF16
 // parts, a.b ~ hi.hi + hi.lo + lo.hi (three BF16 MFMAs, FP32 accumulation),
 // which is ~5x cheaper than the FP32 contraction and accurate to ~1e-4. Each
-// lane keeps exact float scores (top-2 with indices plus its third-best score).
-// From the split errors a per-query bound E on every score error follows; if
+// lane keeps float keys (the score with its low 4 bits replaced by the
+// accumulator row, within 15 units in the last place of the score): the two
+// largest, whose candidates are recovered, and the third largest as the bound
+// of everything left behind. From the split errors and that truncation a
+// per-query bound E on every score error follows; if
 // everything a lane did not keep scores above the kept second best by more
 // than 2E, the true two nearest are among the kept ones and FP32 rescoring of
 // those is exact. Other queries go to a device-side list matched by the FP32
@@ -764,18 +767,9 @@ __device__ inline uint4 load_split8(const float* p, uint4& lo)
     return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
 }
 
-// Max-ordered top-2 of acc = a.b - |b|^2/2 with indices, plus the third value;
-// ties keep the earlier (lower) index.
-__device__ inline void top2_third(float x, int j, float& b1, int& j1, float& b2, int& j2, float& b3)
-{
-    b3 = fmaxf(b3, fminf(b2, x));
-    const bool g1 = x > b1;
-    const bool g2 = x > b2;
-    b2 = g1 ? b1 : (g2 ? x : b2);
-    j2 = g1 ? j1 : (g2 ? j : j2);
-    b1 = g1 ? x : b1;
-    j1 = g1 ? j : j1;
-}
+// Padded candidate rows start their accumulator here instead of -|b|^2/2: a
+// finite value far below any real score (keys stay free of inf and NaN).
+constexpr float kX3Pad = -3.0e38f;
 
 __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
                                     const uint8_t* __restrict__ Bhl, int64_t nB,
@@ -788,8 +782,9 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t cb = (int64_t)chunk * chunk_len;
-    const int64_t ce = (cb + chunk_len < nB) ? cb + chunk_len : nB;
+    // candidate rows cb .. ce - 1 (nB < 2^31: unsigned tile positions cannot wrap)
+    const uint32_t cb = (uint32_t)((int64_t)chunk * chunk_len);
+    const uint32_t ce = (uint32_t)(((int64_t)cb + chunk_len < nB) ? (int64_t)cb + chunk_len : nB);
 
     // queries, set t: dims [16 s + 8 h, +8) of query col as hi and lo BF16
     uint4 qh[2][8], ql[2][8];
@@ -808,29 +803,48 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
             }
         }
     }
-    float b1[2], b2[2], b3[2];
-    int j1[2], j2[2];
+    // Per lane and query set: the two largest keys and the third largest. A
+    // key is the float acc with its low 4 bits replaced by the accumulator row
+    // r (a change of at most 15 units in the last place, which the rescoring
+    // bound allows for), kept with v_max_f32 / v_med3_f32; the tile of each
+    // kept key is recovered once per tile by comparing it with its value
+    // before the tile.
+    // A key of a later tile can equal a kept key bit for bit (same truncated
+    // value and row); the kept pair then holds one candidate twice and the
+    // other one's key may exceed k3, so such a lane reports no bound (-inf)
+    // and its query goes to the FP32 path.
+    float k1[2], k2[2], k3[2];
+    int t1[2], t2[2];
+    bool dup[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        b1[t] = b2[t] = b3[t] = -INFINITY;
-        j1[t] = j2[t] = -1;
+        k1[t] = k2[t] = k3[t] = -INFINITY;
+        t1[t] = t2[t] = -1;
+        dup[t] = false;
     }
 
     // a 32 x 512-byte tile of split rows: thread t moves uint4 number t + 256 k
+    // (row (t + 256 k) / 32) from a uniform base; threads t < 32 also the
+    // accumulator start of row t
     uint4 pf[4];
-    auto fetch = [&](int64_t t0) {
+    float pn = kX3Pad;
+    auto fetch = [&](uint32_t t0) {
+        const uint4* base = reinterpret_cast<const uint4*>(Bhl + (int64_t)t0 * 512);
+        if (ce - t0 >= (uint32_t)kX3CT) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int f = tid + 256 * k;
-            const int r = f >> 5, c16 = f & 31;
-            const int64_t j = t0 + r;
-            pf[k] = (j < ce) ? reinterpret_cast<const uint4*>(Bhl + j * 512)[c16]
-                             : make_uint4(0u, 0u, 0u, 0u);
+            for (int k = 0; k < 4; ++k) pf[k] = base[tid + 256 * k];
+            if (tid < kX3CT) pn = -0.5f * nrmB[t0 + tid];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                pf[k] = ((uint32_t)((tid + 256 * k) >> 5) < ce - t0) ? base[tid + 256 * k]
+                                                                      : make_uint4(0u, 0u, 0u, 0u);
+            if (tid < kX3CT) pn = ((uint32_t)tid < ce - t0) ? -0.5f * nrmB[t0 + tid] : kX3Pad;
         }
     };
     if (cb < ce) fetch(cb);
 
-    for (int64_t t0 = cb; t0 < ce; t0 += kX3CT) {
+    for (uint32_t t0 = cb; t0 < ce; t0 += kX3CT) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -838,9 +852,9 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
             const int r = f >> 5, c16 = f & 31;
             *reinterpret_cast<uint4*>(&tile[r * kX3Row + c16 * 16]) = pf[k];
         }
-        if (tid < kX3CT) tinit[tid] = (t0 + tid < ce) ? -0.5f * nrmB[t0 + tid] : -INFINITY;
+        if (tid < kX3CT) tinit[tid] = pn;
         __syncthreads();
-        if (t0 + kX3CT < ce) fetch(t0 + kX3CT);
+        if (ce - t0 > (uint32_t)kX3CT) fetch(t0 + kX3CT);
 
         // accumulators start at -|b|^2 / 2 of their candidate row
         floatx16 acc[2];
@@ -866,23 +880,56 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
                     __builtin_bit_cast(bf16x8, bh), __builtin_bit_cast(bf16x8, ql[t][s]), acc[t], 0, 0, 0);
             }
         }
+        // result row (candidate) of accumulator r in this lane: 8 (r/4) + 4 h + r % 4
+        float p1[2], p2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            p1[t] = k1[t];
+            p2[t] = k2[t];
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int cl = 8 * (r >> 2) + 4 * h + (r & 3);
-            const int j = (int)(t0 + cl);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) top2_third(acc[t][r], j, b1[t], j1[t], b2[t], j2[t], b3[t]);
+            for (int t = 0; t < 2; ++t) {
+                const float x = __int_as_float((__float_as_int(acc[t][r]) & -16) | r);
+                k3[t] = __builtin_amdgcn_fmed3f(x, k2[t], k3[t]);   // k1 >= k2 >= k3
+                k2[t] = __builtin_amdgcn_fmed3f(x, k1[t], k2[t]);
+                k1[t] = fmaxf(x, k1[t]);
+            }
+        }
+        // a kept key bit-equal to an earlier kept key is that one; else it is new
+        const int tt = (int)(t0 - cb);   // chunk-relative tile start
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int b1 = __float_as_int(k1[t]), b2 = __float_as_int(k2[t]);
+            t2[t] = (b2 == __float_as_int(p2[t])) ? t2[t] : ((b2 == __float_as_int(p1[t])) ? t1[t] : tt);
+            t1[t] = (b1 == __float_as_int(p1[t])) ? t1[t] : tt;
+            dup[t] = dup[t] || (b1 == b2 && k2[t] != -INFINITY);
         }
     }
+    // key -> (candidate index, score -2 acc); empty slots and padded rows give
+    // index -1 and score +inf
+    auto unpack = [&](float k, int t, int& j, float& sc) {
+        const int r = __float_as_int(k) & 15;
+        const bool real = t >= 0 && k > 0.5f * kX3Pad;
+        j = real ? (int)cb + t + 8 * (r >> 2) + 4 * h + (r & 3) : -1;
+        sc = real ? -2.0f * k : INFINITY;
+    };
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         if (qi[t] < nA) {
             const int64_t o = (qi[t] * chunks + chunk) * 4 + 2 * h;
-            cidx[o] = j1[t];
-            cidx[o + 1] = j2[t];
-            cscore[o] = -2.0f * b1[t];
-            cscore[o + 1] = -2.0f * b2[t];
-            cthird[(qi[t] * chunks + chunk) * 2 + h] = -2.0f * b3[t];
+            int ja, jb;
+            float sa, sb;
+            unpack(k1[t], t1[t], ja, sa);
+            unpack(k2[t], t2[t], jb, sb);
+            cidx[o] = ja;
+            cidx[o + 1] = jb;
+            cscore[o] = sa;
+            cscore[o + 1] = sb;
+            // no real candidate left behind: +inf; a duplicated key: -inf
+            cthird[(qi[t] * chunks + chunk) * 2 + h] =
+                dup[t] ? -INFINITY : ((k3[t] > 0.5f * kX3Pad) ? -2.0f * k3[t] : INFINITY);
         }
     }
 }
@@ -927,8 +974,12 @@ __device__ inline void rescore_x3_query(
     const float gamma = 385.0f * 5.9604645e-8f;   // FP32 additions along one accumulator chain
     const float dot_err = aln * bln + (an + arn) * brn + arn * (bn + brn)
                           + gamma * (3.0f * (an + arn) * (bn + brn) + 0.5f * bn2);
-    // score = -2 acc; |b|^2 itself carries the FP32 error of a 128-term sum
-    const float E = 2.02f * dot_err + 1e-5f * bn2 + 1e-7f;
+    // score = -2 acc; |b|^2 itself carries the FP32 error of a 128-term sum.
+    // The contraction kept keys, not scores: each kept and third value is
+    // off by at most 15 units in the last place of |acc| <= M, i.e. by
+    // 30 x 2^-23 M <= 2^-18 M in score units (2^-17 M allowed).
+    const float M = 0.5f * bn2 + an * bn + dot_err;
+    const float E = 2.02f * dot_err + 1e-5f * bn2 + 1e-7f + 7.62939453125e-6f * M;
     // T: best score any group may have left behind (its third best)
     float m1 = sc, m2 = INFINITY;
 #pragma unroll
