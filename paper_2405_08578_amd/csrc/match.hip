@@ -281,11 +281,15 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             kb2 = smed3(xb, kb1, kb2);
             kb1 = min(xb, kb1);
         }
-        // a kept key equal to an earlier kept key is that one; else it is new
+        // A kept key equal to its value before the tile is that candidate; the
+        // second key equal to the old first one is the old first candidate,
+        // unless the first key kept that value too: then this tile produced a
+        // key identical to it (same truncated distance and row) and the
+        // second slot takes the tile's candidate. Else the key is new.
         const int tt = (int)(t0 - cb);   // chunk-relative tile start
-        ta2 = (ka2 == pa2) ? ta2 : ((ka2 == pa1) ? ta1 : tt);
+        ta2 = (ka2 == pa2) ? ta2 : ((ka2 == pa1 && ka1 != pa1) ? ta1 : tt);
         ta1 = (ka1 == pa1) ? ta1 : tt;
-        tb2 = (kb2 == pb2) ? tb2 : ((kb2 == pb1) ? tb1 : tt);
+        tb2 = (kb2 == pb2) ? tb2 : ((kb2 == pb1 && kb1 != pb1) ? tb1 : tt);
         tb1 = (kb1 == pb1) ? tb1 : tt;
     }
 
@@ -809,18 +813,12 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
     // bound allows for), kept with v_max_f32 / v_med3_f32; the tile of each
     // kept key is recovered once per tile by comparing it with its value
     // before the tile.
-    // A key of a later tile can equal a kept key bit for bit (same truncated
-    // value and row); the kept pair then holds one candidate twice and the
-    // other one's key may exceed k3, so such a lane reports no bound (-inf)
-    // and its query goes to the FP32 path.
     float k1[2], k2[2], k3[2];
     int t1[2], t2[2];
-    bool dup[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         k1[t] = k2[t] = k3[t] = -INFINITY;
         t1[t] = t2[t] = -1;
-        dup[t] = false;
     }
 
     // a 32 x 512-byte tile of split rows: thread t moves uint4 number t + 256 k
@@ -897,14 +895,19 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
                 k1[t] = fmaxf(x, k1[t]);
             }
         }
-        // a kept key bit-equal to an earlier kept key is that one; else it is new
+        // tile of each kept key, as in the FP32 path: a key bit-equal to its
+        // value before the tile is that candidate; the second key equal to the
+        // old first one is the old first candidate unless the first key kept
+        // that value too (a bit-identical key of this tile); else it is new.
+        // So the kept pair never holds one candidate twice, and every other
+        // candidate's key is at most k3.
         const int tt = (int)(t0 - cb);   // chunk-relative tile start
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int b1 = __float_as_int(k1[t]), b2 = __float_as_int(k2[t]);
-            t2[t] = (b2 == __float_as_int(p2[t])) ? t2[t] : ((b2 == __float_as_int(p1[t])) ? t1[t] : tt);
-            t1[t] = (b1 == __float_as_int(p1[t])) ? t1[t] : tt;
-            dup[t] = dup[t] || (b1 == b2 && k2[t] != -INFINITY);
+            const int o1 = __float_as_int(p1[t]), o2 = __float_as_int(p2[t]);
+            t2[t] = (b2 == o2) ? t2[t] : ((b2 == o1 && b1 != o1) ? t1[t] : tt);
+            t1[t] = (b1 == o1) ? t1[t] : tt;
         }
     }
     // key -> (candidate index, score -2 acc); empty slots and padded rows give
@@ -927,9 +930,8 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
             cidx[o + 1] = jb;
             cscore[o] = sa;
             cscore[o + 1] = sb;
-            // no real candidate left behind: +inf; a duplicated key: -inf
-            cthird[(qi[t] * chunks + chunk) * 2 + h] =
-                dup[t] ? -INFINITY : ((k3[t] > 0.5f * kX3Pad) ? -2.0f * k3[t] : INFINITY);
+            // no real candidate left behind: +inf
+            cthird[(qi[t] * chunks + chunk) * 2 + h] = (k3[t] > 0.5f * kX3Pad) ? -2.0f * k3[t] : INFINITY;
         }
     }
 }

@@ -79,6 +79,26 @@ def test_match_exact_cases(gpu):
     assert g["match"][1] == -1 and g["d1"][1] == 0.0 and g["d2"][1] == 0.0
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("pos", [(5, 37), (5, 69), (36, 100)])
+def test_match_identical_candidates_in_two_tiles(gpu, precision, pos):
+    # Candidates pos[0] and pos[1] sit at the same row of different 32-row
+    # candidate tiles and equal the query, so the contraction produces
+    # bit-identical keys for them in one lane: both must be kept (d1 = d2 = 0,
+    # a tie, rejected), not one of them twice.
+    rng = np.random.Generator(np.random.PCG64(21))
+    B = synth.random_unit_rows(160, 128, rng).astype(np.float32)
+    A = synth.random_unit_rows(3, 128, rng).astype(np.float32)
+    B[pos[0]] = A[0]
+    B[pos[1]] = A[0]
+    say("identical candidates in two tiles", precision, pos)
+    g = run_match(gpu, A, B, precision=precision)
+    assert g["d1"][0] == 0.0 and g["d2"][0] == 0.0 and g["match"][0] == -1
+    o = oracle.match(A.astype(np.float64), B.astype(np.float64))
+    assert o["match"][0] == -1
+    assert np.array_equal(g["match"][1:], o["match"][1:])
+
+
 def test_match_degenerate_sizes(gpu):
     import torch
     rng = np.random.Generator(np.random.PCG64(3))
