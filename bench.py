@@ -54,26 +54,44 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_topk_f32_2600x1600_pair_traffic.md")
 MATCH_SRC = os.path.join(ROOT, "paper_2405_08578_amd", "csrc", "match.hip")
+DESC_COUNTERS_FILE = os.path.join(ROOT, "profiles", "orient_describe_2600x1600_pair_counters.md")
+DESC_SRC = os.path.join(ROOT, "paper_2405_08578_amd", "csrc", "describe.hip")
+# VALU issue ceiling: 1,024 SIMDs x 2.4 GHz, one wave64 VALU instruction per
+# 4 cycles on a 16-lane SIMD
+PEAK_VALU_GINSTR = 1024 * 2.4 / 4
+
+
+def committed_figure(path, src, src_key, key):
+    """A figure from a committed PMC summary ("- key: value" lines), or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get(src_key) != sha:
+        return None
+    try:
+        return float(vals[key])
+    except (KeyError, ValueError):
+        return None
 
 
 def measured_traffic():
     """HBM bytes per launch of the contraction kernel from the committed PMC
     summary, or None when the kernel source changed since it was taken."""
-    import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    sha = hashlib.sha256(open(MATCH_SRC, "rb").read()).hexdigest()
-    vals = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and line.strip().startswith("- "):
-            k, v = line.strip()[2:].split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("match.hip sha256") != sha:
-        return None
-    try:
-        return float(vals["traffic bytes per launch"])
-    except (KeyError, ValueError):
-        return None
+    return committed_figure(TRAFFIC_FILE, MATCH_SRC, "match.hip sha256", "traffic bytes per launch")
+
+
+def describe_valu_instructions():
+    """Wave-level VALU instructions of the describe step on the pair (both
+    images), from the committed counter summary; None when stale."""
+    return committed_figure(DESC_COUNTERS_FILE, DESC_SRC, "describe.hip sha256",
+                            "VALU instructions per pair step")
 
 
 def cpu_baseline(pair, Ls, reps=3):
@@ -468,6 +486,17 @@ def main():
              "detect_GBps": round(det_bytes / (kt["detect"]["ms_per_step"] * 1e-3) / 1e9, 1),
              "gradient_GBps": round(grad_bytes / (kt["gradient"]["ms_per_step"] * 1e-3) / 1e9, 1),
              "describe_keypoints_per_s": round(2 * n_kp / (kt["describe"]["ms_per_step"] * 1e-3), 0)}
+    # describe against its own roof, the VALU issue rate: the counted VALU
+    # instructions of the step over its live event time
+    n_valu = describe_valu_instructions()
+    if n_valu is not None:
+        g = n_valu / (kt["describe"]["ms_per_step"] * 1e-3) / 1e9
+        rates["describe_valu"] = {"bound": "alu", "achieved": round(g, 1), "peak": PEAK_VALU_GINSTR,
+                                  "unit": "G wave64 VALU instructions/s",
+                                  "frac": round(g / PEAK_VALU_GINSTR, 4),
+                                  "instructions": n_valu}
+    else:
+        rates["describe_valu"] = None
 
     out = {
         "metric": METRIC,

@@ -36,3 +36,28 @@ def test_traffic_follows_the_kernel_source_hash():
         assert t is not None and t > 48777104          # above the algorithmic bytes
     else:
         assert t is None
+
+
+def test_describe_valu_count_follows_the_kernel_source_hash():
+    sha = hashlib.sha256(open(bench.DESC_SRC, "rb").read()).hexdigest()
+    recorded = None
+    for line in open(bench.DESC_COUNTERS_FILE):
+        if line.strip().startswith("- describe.hip sha256:"):
+            recorded = line.split(":", 1)[1].strip()
+    n = bench.describe_valu_instructions()
+    if recorded == sha:
+        assert n is not None and n > 1e6
+    else:
+        assert n is None
+
+
+def test_committed_figure_reads_key_lines(tmp_path):
+    src = tmp_path / "k.hip"
+    src.write_text("kernel")
+    sha = hashlib.sha256(b"kernel").hexdigest()
+    f = tmp_path / "s.md"
+    f.write_text(f"# t\n\n- k.hip sha256: {sha}\n- figure: 12.5\n")
+    assert bench.committed_figure(str(f), str(src), "k.hip sha256", "figure") == 12.5
+    assert bench.committed_figure(str(f), str(src), "k.hip sha256", "other") is None
+    src.write_text("changed")
+    assert bench.committed_figure(str(f), str(src), "k.hip sha256", "figure") is None
