@@ -99,6 +99,27 @@ def test_match_identical_candidates_in_two_tiles(gpu, precision, pos):
     assert np.array_equal(g["match"][1:], o["match"][1:])
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("scale,seed", [(1e-3, 31), (1.0, 32), (1e3, 33)])
+def test_match_signed_scaled_sets(gpu, precision, scale, seed):
+    # general FP32 rows: signed components, norms spread over a factor of ~10
+    # around `scale`, queries near some candidates; the lane keys hold squared
+    # distances of any magnitude
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nA, nB = 700, 1500
+    B = synth.random_unit_rows(nB, 128, rng, nonneg=False)
+    B *= scale * np.exp(rng.uniform(-1.2, 1.2, (nB, 1)))
+    idx = rng.integers(0, nB, nA)
+    noise = rng.uniform(0.02, 1.5, (nA, 1)) * np.linalg.norm(B[idx], axis=1, keepdims=True) / 11.3
+    A = B[idx] + rng.normal(0.0, 1.0, (nA, 128)) * noise
+    A, B = A.astype(np.float32), B.astype(np.float32)
+    say("signed scaled sets", precision, scale, seed)
+    g = run_match(gpu, A, B, precision=precision)
+    check_rule_i(A, B, g)
+    n = int((g["match"] >= 0).sum())
+    assert 100 < n < 650
+
+
 def test_match_degenerate_sizes(gpu):
     import torch
     rng = np.random.Generator(np.random.PCG64(3))
