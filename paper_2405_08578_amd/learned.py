@@ -23,8 +23,12 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
-from . import (Params, ScorerTrainer, describe, describe_selected, detect, keep_count, match,
-               prune, ransac, score, scorer_gather, SCORER_PARAMS)
+import math
+
+from . import (DESC_DIM, Params, ScorerTrainer, describe, describe_selected,
+               describe_workspace_size, detect, empty_keypoints, keep_count, match, match_params,
+               match_workspace_size, num_keypoints, prune, ransac, score, scorer_gather,
+               SCORER_PARAMS)
 
 WEIGHTS_VERSION = 1
 RANSAC_ITERS = 2000
@@ -97,6 +101,97 @@ def learned_gpu_batch(pairs, P: Params, weights, num: int = 3, den: int = 10,
     r = match(desc[0::2], desc[1::2], precision=precision)
     return [{"kps": kps[2 * i:2 * i + 2], "sel": sel[2 * i:2 * i + 2], "match": r[i]["match"]}
             for i in range(len(pairs))]
+
+
+class BatchPath:
+    """The plain (weights=None) or learned path over a fixed list of image
+    pairs [[A, B], ...] with every buffer allocated once: keypoint slots,
+    scores, kept-slot lists, orientations, descriptors, both workspaces and the
+    match lists. A step is then a fixed sequence of library calls -- plain:
+    detect, describe, match; learned: detect, score, prune, describe_selected,
+    match -- that allocates nothing and never synchronises, so it can run
+    eagerly or be captured once into a HIP graph and replayed (the launch
+    sequence depends only on the image shapes). results() returns the same
+    per-pair dicts as plain_gpu_batch / learned_gpu_batch."""
+
+    def __init__(self, pairs, params: Params, weights=None, num: int = 3, den: int = 10,
+                 precision: int = 0, ratio: float = 0.8, abs_thresh: float = math.inf):
+        import torch
+        self.images = [t for pr in pairs for t in pr]
+        self.n_pairs = len(pairs)
+        self.params = params
+        self.weights = weights
+        self.precision = precision
+        self.ratio = ratio
+        self.abs_thresh = abs_thresh
+        dev = self.images[0].device
+        self.device = dev
+        n_kp = [num_keypoints(t.shape[0], t.shape[1], params) for t in self.images]
+        self.kps = [empty_keypoints(n, dev) for n in n_kp]
+        if weights is not None:
+            self.scores = [torch.empty(n, dtype=torch.float32, device=dev) for n in n_kp]
+            self.keep = [keep_count(n, num, den) for n in n_kp]
+            self.sel = [torch.empty(k, dtype=torch.int32, device=dev) for k in self.keep]
+            rows = self.keep
+        else:
+            rows = n_kp
+        self.theta = [torch.empty(r, dtype=torch.float32, device=dev) for r in rows]
+        self.desc = [torch.empty((r, DESC_DIM), dtype=torch.float32, device=dev) for r in rows]
+        self.dws = torch.empty(max(describe_workspace_size(self.images, params), 256),
+                               dtype=torch.uint8, device=dev)
+        mp = match_params(ratio, abs_thresh, precision, 0, None)
+        need = match_workspace_size(rows[0::2], rows[1::2], mp)
+        self.mws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        self.out = [{"match": torch.empty(rows[2 * i], dtype=torch.int32, device=dev),
+                     "d1": torch.empty(rows[2 * i], dtype=torch.float32, device=dev),
+                     "d2": torch.empty(rows[2 * i], dtype=torch.float32, device=dev)}
+                    for i in range(self.n_pairs)]
+        self.graph = None
+
+    def run(self, stream=None):
+        """Enqueue one step on `stream` (default: the current stream)."""
+        P = self.params
+        detect(self.images, P, out=self.kps, stream=stream)
+        if self.weights is not None:
+            score(self.images, self.kps, P, self.weights, out=self.scores, stream=stream)
+            prune(self.scores, self.keep, out=self.sel, stream=stream)
+            describe_selected(self.images, self.kps, P, self.sel, workspace=self.dws,
+                              theta=self.theta, desc=self.desc, stream=stream)
+        else:
+            describe(self.images, self.kps, P, workspace=self.dws, theta=self.theta,
+                     desc=self.desc, stream=stream)
+        match(self.desc[0::2], self.desc[1::2], ratio=self.ratio, abs_thresh=self.abs_thresh,
+              precision=self.precision, workspace=self.mws, out=self.out, stream=stream)
+
+    def capture(self, warmup: int = 1):
+        """Capture one step into a graph (after `warmup` eager steps on a side
+        stream, as graph capture requires)."""
+        import torch
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def results(self):
+        res = []
+        for i in range(self.n_pairs):
+            r = {"kps": self.kps[2 * i:2 * i + 2], "match": self.out[i]["match"]}
+            if self.weights is not None:
+                r["sel"] = self.sel[2 * i:2 * i + 2]
+            res.append(r)
+        return res
 
 
 def gt_consistent(xyA: np.ndarray, xyB: np.ndarray, H_true: np.ndarray,

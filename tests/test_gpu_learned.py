@@ -75,3 +75,44 @@ def test_batched_paths_equal_per_pair(gpu):
         assert np.array_equal(bl[k]["match"].cpu().numpy(), sl["match"].cpu().numpy())
         for a, b in zip(bl[k]["sel"], sl["sel"]):
             assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_batch_path_eager_and_graph_replays(gpu):
+    # The preallocated step of both paths, run eagerly and as replays of one
+    # captured graph (outputs clobbered and other eager work between the
+    # replays), equals the allocating batch functions bit for bit.
+    import torch
+    pairs = [synth.config_pair(0), synth.make_mixed_pair((1100, 825, 430, 5))]
+    P = lp.Params([16, 32, 64])
+    imgs = [[to_dev(p.A, gpu), to_dev(p.B, gpu)] for p in pairs]
+    w = load(gpu)
+    say("batch path eager / graph")
+    refs = {None: L.plain_gpu_batch(imgs, P), "w": L.learned_gpu_batch(imgs, P, w)}
+
+    def same(res, ref):
+        for a, b in zip(res, ref):
+            assert np.array_equal(a["match"].cpu().numpy(), b["match"].cpu().numpy())
+            for u, v in zip(a["kps"], b["kps"]):
+                assert np.array_equal(u["x"].cpu().numpy(), v["x"].cpu().numpy())
+            if "sel" in b:
+                for u, v in zip(a["sel"], b["sel"]):
+                    assert np.array_equal(u.cpu().numpy(), v.cpu().numpy())
+
+    for key, weights in ((None, None), ("w", w)):
+        bp = L.BatchPath(imgs, P, weights=weights)
+        bp.run()
+        torch.cuda.synchronize()
+        same(bp.results(), refs[key])
+        bp.capture()
+        for rep in range(3):
+            for o in bp.out:
+                o["match"].fill_(-7)
+            if weights is not None:
+                for s in bp.sel:
+                    s.fill_(-7)
+            L.plain_gpu_batch(imgs[:1], P)
+            torch.cuda.synchronize()
+            bp.replay()
+            torch.cuda.synchronize()
+            say("replay", key, rep)
+            same(bp.results(), refs[key])
