@@ -344,8 +344,8 @@ def bench_learned(args, dev, pairs):
     # one captured HIP graph (the GPU work alone); the graph figures are the
     # reported pairs/s of both paths.
     steps = max(1, min(3, args.steps // 5))
-    out = {}
-    for name, bp in (("plain", L.BatchPath(imgs, P)), ("learned", L.BatchPath(imgs, P, weights=w))):
+
+    def timed(bp):
         bp.run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -360,7 +360,27 @@ def bench_learned(args, dev, pairs):
         for _ in range(steps):
             bp.replay()
         torch.cuda.synchronize()
-        out[name] = ((time.perf_counter() - t0) * 1000.0 / steps, bp.results(), eager_ms)
+        return (time.perf_counter() - t0) * 1000.0 / steps, eager_ms
+
+    out = {}
+    lists = {}
+    for name, weights in (("plain", None), ("learned", w)):
+        bp = L.BatchPath(imgs, P, weights=weights)
+        g_ms, e_ms = timed(bp)
+        out[name] = (g_ms, bp.results(), e_ms)
+        lists[name] = [o["match"].cpu().numpy() for o in bp.out]
+        del bp
+    # the same two paths with the certified split-BF16 matcher (its lists
+    # equal the FP32 path's): graph replays only, lists compared
+    split = {}
+    for name, weights in (("plain", None), ("learned", w)):
+        bp = L.BatchPath(imgs, P, weights=weights, precision=3)
+        g_ms, _ = timed(bp)
+        same = sum(int((o["match"].cpu().numpy() == m).sum()) for o, m in zip(bp.out, lists[name]))
+        total = sum(len(m) for m in lists[name])
+        split[name] = (g_ms, same / max(total, 1))
+        del bp
+    torch.cuda.empty_cache()
     rows = []
     t0 = time.perf_counter()
     for k, p in enumerate(pairs):
@@ -393,6 +413,11 @@ def bench_learned(args, dev, pairs):
             "fallbacks": int(r[:, 4].sum()),
             "matches_plain": int(r[:, 5].sum()), "matches_learned": int(r[:, 6].sum()),
             "host_ransac_ms_per_pair": round(1000.0 * t_host, 2),
+            "split_bf16x3_certified": {
+                "plain_pairs_per_s": round(len(pairs) * 1000.0 / split["plain"][0], 2),
+                "learned_pairs_per_s": round(len(pairs) * 1000.0 / split["learned"][0], 2),
+                "speedup": round(split["plain"][0] / split["learned"][0], 2),
+                "list_agreement_with_fp32": {k: round(v[1], 6) for k, v in split.items()}},
             "weights_sha256": info["sha256"][:16]}
 
 
