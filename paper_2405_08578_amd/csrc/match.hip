@@ -271,15 +271,21 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
         // result row (candidate) of accumulator r in this lane: 8 (r/4) + 4 h + r % 4;
         // squared distance |b|^2 - 2 acc = |a|^2 + |b|^2 - 2 a.b
         const int pa1 = ka1, pa2 = ka2, pb1 = kb1, pb2 = kb2;
+        // two rows at a time: for k1 <= k2 and new keys x, y the two smallest
+        // of all four are min3(k1, x, y) and min(k2, med3(k1, x, y)) -- three
+        // instructions for two keys
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float nrm = tnrm[8 * (r >> 2) + 4 * h + (r & 3)];
-            const int xa = (__float_as_int(fmaf(-2.0f, acc0[r], nrm)) & -16) | r;
-            const int xb = (__float_as_int(fmaf(-2.0f, acc1[r], nrm)) & -16) | r;
-            ka2 = smed3(xa, ka1, ka2);
-            ka1 = min(xa, ka1);
-            kb2 = smed3(xb, kb1, kb2);
-            kb1 = min(xb, kb1);
+        for (int r = 0; r < 16; r += 2) {
+            const float n0 = tnrm[8 * (r >> 2) + 4 * h + (r & 3)];
+            const float n1 = tnrm[8 * (r >> 2) + 4 * h + (r & 3) + 1];
+            const int xa = (__float_as_int(fmaf(-2.0f, acc0[r], n0)) & -16) | r;
+            const int ya = (__float_as_int(fmaf(-2.0f, acc0[r + 1], n1)) & -16) | (r + 1);
+            const int xb = (__float_as_int(fmaf(-2.0f, acc1[r], n0)) & -16) | r;
+            const int yb = (__float_as_int(fmaf(-2.0f, acc1[r + 1], n1)) & -16) | (r + 1);
+            ka2 = min(ka2, smed3(ka1, xa, ya));
+            ka1 = min(ka1, min(xa, ya));
+            kb2 = min(kb2, smed3(kb1, xb, yb));
+            kb1 = min(kb1, min(xb, yb));
         }
         // A kept key equal to its value before the tile is that candidate; the
         // second key equal to the old first one is the old first candidate,
