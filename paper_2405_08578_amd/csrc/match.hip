@@ -626,22 +626,38 @@ __global__ __launch_bounds__(256, 1) void match_topk_lp_kernel(
                     }
                 }
             }
-            // epilogue: key = (score bits & ~mask) | index in chunk, top-2 by min / med3
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            // epilogue: key = (score bits & ~mask) | index in chunk, top-K by
+            // min / med3 (keys are unique)
+            auto lp_key = [&](int t, int r) {
                 const int cl = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const float nb = tnb[cl];
-                const uint32_t idx = local0 + (uint32_t)cl;
+                const float sc = (P == 1) ? fmaf(-2.0f, acc[t][r], tnb[cl])
+                                          : fmaf(qs2[t] * tsb[cl], acc[t][r], tnb[cl]);
+                return (__float_as_uint(sc) & ~idx_mask) | (local0 + (uint32_t)cl);
+            };
+            if constexpr (K == 2) {
+                // two rows at a time: for k1 <= k2 and new keys x, y the two
+                // smallest of all four are min3(k1, x, y) and min(k2, med3(k1, x, y))
 #pragma unroll
-                for (int t = 0; t < kLpSets; ++t) {
-                    const float sc = (P == 1) ? fmaf(-2.0f, acc[t][r], nb)
-                                              : fmaf(qs2[t] * tsb[cl], acc[t][r], nb);
-                    const uint32_t key = (__float_as_uint(sc) & ~idx_mask) | idx;
-                    // sorted insertion (k1 <= k2 <= k3, keys unique): the new
-                    // i-th smallest is key clamped to [k(i-1), k(i)]
-                    if (K == 3) k3[t] = umed3(key, k2[t], k3[t]);
-                    k2[t] = umed3(key, k1[t], k2[t]);
-                    k1[t] = min(k1[t], key);
+                for (int r = 0; r < 16; r += 2) {
+#pragma unroll
+                    for (int t = 0; t < kLpSets; ++t) {
+                        const uint32_t x = lp_key(t, r), y = lp_key(t, r + 1);
+                        k2[t] = min(k2[t], umed3(k1[t], x, y));
+                        k1[t] = min(k1[t], min(x, y));
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+#pragma unroll
+                    for (int t = 0; t < kLpSets; ++t) {
+                        // sorted insertion (k1 <= k2 <= k3): the new i-th
+                        // smallest is the key clamped to [k(i-1), k(i)]
+                        const uint32_t key = lp_key(t, r);
+                        k3[t] = umed3(key, k2[t], k3[t]);
+                        k2[t] = umed3(key, k1[t], k2[t]);
+                        k1[t] = min(k1[t], key);
+                    }
                 }
             }
         }

@@ -178,14 +178,16 @@ __global__ __launch_bounds__(256, 2) void match_topk_u8_kernel(
                 const uint4 v = *reinterpret_cast<const uint4*>(&tc[8 * q4 + 4 * h]);
                 cr[4 * q4 + 0] = v.x; cr[4 * q4 + 1] = v.y; cr[4 * q4 + 2] = v.z; cr[4 * q4 + 3] = v.w;
             }
+            // two rows at a time: for k1 <= k2 and new keys x, y the two
+            // smallest of all four are min3(k1, x, y) and min(k2, med3(k1, x, y))
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < 16; r += 2) {
 #pragma unroll
                 for (int t = 0; t < kU8Sets; ++t) {
-                    const uint32_t key = cr[r] + ((uint32_t)acc[t][r] << 9);
-                    const uint32_t m = min(k1[t], key);
-                    k2[t] = umed3(k1[t], k2[t], key);
-                    k1[t] = m;
+                    const uint32_t x = cr[r] + ((uint32_t)acc[t][r] << 9);
+                    const uint32_t y = cr[r + 1] + ((uint32_t)acc[t][r + 1] << 9);
+                    k2[t] = min(k2[t], umed3(k1[t], x, y));
+                    k1[t] = min(k1[t], min(x, y));
                 }
             }
         }
