@@ -393,9 +393,10 @@ __device__ inline void rescore_f32_query(const float* __restrict__ A, const floa
             }
         }
     }
-    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
-    float e1 = INFINITY, e2 = INFINITY;
-    int j1 = -1, j2 = -1;
+    // the (up to) 4 best entries by contraction score, selected first ...
+    int pick[4];
+    int cnt = 0;
+#pragma unroll
     for (int round = 0; round < 4; ++round) {
         // this lane's best entry, then the wavefront's
         float bs = sc[0];
@@ -415,11 +416,30 @@ __device__ inline void rescore_f32_query(const float* __restrict__ A, const floa
                 bi = oi;
             }
         }
-        if (bi == 0x7FFFFFFF || bs == INFINITY) break;
+        pick[round] = bi;
+        if (bi != 0x7FFFFFFF && bs != INFINITY) cnt = round + 1;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (id[k] == bi) sc[k] = INFINITY, id[k] = 0x7FFFFFFF;   // taken (ids are unique)
-        best2_insert(sqdist(a0, a1, B, bi, lane), bi, e1, j1, e2, j2);
+    }
+    // ... then their rows loaded together (one memory latency instead of four)
+    // and their distances computed directly; the top-2 by (distance, index)
+    // does not depend on the insertion order
+    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
+    float b0[4], b1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b0[k] = (k < cnt) ? B[(int64_t)pick[k] * 128 + lane] : 0.0f;
+        b1[k] = (k < cnt) ? B[(int64_t)pick[k] * 128 + 64 + lane] : 0.0f;
+    }
+    float e1 = INFINITY, e2 = INFINITY;
+    int j1 = -1, j2 = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < cnt) {
+            const float x0 = a0 - b0[k], x1 = a1 - b1[k];
+            best2_insert(wave_sum(x0 * x0 + x1 * x1), pick[k], e1, j1, e2, j2);
+        }
     }
     if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
 }
@@ -695,9 +715,10 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
             j = (int64_t)(lane / (2 * K)) * chunk_len + (key & idx_mask);
         }
     }
-    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
-    float e1 = INFINITY, e2 = INFINITY;
-    int j1 = -1, j2 = -1;
+    // the kLpRescore best kept keys, selected first ...
+    int64_t pick[kLpRescore];
+    int cnt = 0;
+#pragma unroll
     for (int round = 0; round < kLpRescore; ++round) {
         float bs = sc;
         int bl = lane;
@@ -710,10 +731,27 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
                 bl = ol;
             }
         }
-        if (bs == INFINITY) break;
+        if (bs != INFINITY) cnt = round + 1;
         if (lane == bl) sc = INFINITY;
-        const int64_t jj = __shfl(j, bl);
-        best2_insert(sqdist(a0, a1, B, jj, lane), (int)jj, e1, j1, e2, j2);
+        pick[round] = __shfl(j, bl);
+    }
+    // ... then their rows loaded together and their distances computed
+    // directly; the top-2 by (distance, index) does not depend on the order
+    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
+    float b0[kLpRescore], b1[kLpRescore];
+#pragma unroll
+    for (int k = 0; k < kLpRescore; ++k) {
+        b0[k] = (k < cnt) ? B[pick[k] * 128 + lane] : 0.0f;
+        b1[k] = (k < cnt) ? B[pick[k] * 128 + 64 + lane] : 0.0f;
+    }
+    float e1 = INFINITY, e2 = INFINITY;
+    int j1 = -1, j2 = -1;
+#pragma unroll
+    for (int k = 0; k < kLpRescore; ++k) {
+        if (k < cnt) {
+            const float x0 = a0 - b0[k], x1 = a1 - b1[k];
+            best2_insert(wave_sum(x0 * x0 + x1 * x1), (int)pick[k], e1, j1, e2, j2);
+        }
     }
     if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
 }
