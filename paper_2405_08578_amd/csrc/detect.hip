@@ -46,6 +46,21 @@ struct DetectArgs {
 
 constexpr int kThreads = 256;
 
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+
+// Lane-wise max / min of two pairs of 16-bit keys (v_pk_max_u16 / v_pk_min_u16).
+__device__ inline uint32_t pk_max(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(ushort2v, a),
+                                                                  __builtin_bit_cast(ushort2v, b)));
+}
+
+__device__ inline uint32_t pk_min(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(ushort2v, a),
+                                                                  __builtin_bit_cast(ushort2v, b)));
+}
+
 __device__ inline void write_kp(const DetectImg& I, int s, int64_t slot, int ox, int oy,
                                 uint32_t key, uint32_t sum, uint32_t n, int8_t type)
 {
@@ -79,7 +94,25 @@ __global__ __launch_bounds__(kThreads) void detect_kernel(DetectArgs args)
     // ---- stage the tile in LDS ----
     {
         const uint8_t* tile0 = I.data + (int64_t)oy * I.pitch + ox;
-        const bool al4 = ((reinterpret_cast<uintptr_t>(tile0) | (uintptr_t)I.pitch) & 3u) == 0;
+        const uintptr_t al = reinterpret_cast<uintptr_t>(tile0) | (uintptr_t)I.pitch;
+        const bool al4 = (al & 3u) == 0;
+        // 16- or 8-byte row pieces where the tile's address, the pitch and
+        // the tile's width allow them (the LDS tile starts 16-byte aligned)
+        if ((al & 15u) == 0 && (Tp & 15) == 0 && (tw & 15) == 0) {
+            const int gpr = tw / 16;
+            for (int idx = tid; idx < th * gpr; idx += kThreads) {
+                const int r = idx / gpr, c = (idx - r * gpr) * 16;
+                *reinterpret_cast<uint4*>(pix + r * Tp + c) =
+                    *reinterpret_cast<const uint4*>(tile0 + (int64_t)r * I.pitch + c);
+            }
+        } else if ((al & 7u) == 0 && (Tp & 7) == 0 && (tw & 7) == 0) {
+            const int gpr = tw / 8;
+            for (int idx = tid; idx < th * gpr; idx += kThreads) {
+                const int r = idx / gpr, c = (idx - r * gpr) * 8;
+                *reinterpret_cast<uint2*>(pix + r * Tp + c) =
+                    *reinterpret_cast<const uint2*>(tile0 + (int64_t)r * I.pitch + c);
+            }
+        } else {
         const int gpr = Tp / 4;
         for (int idx = tid; idx < th * gpr; idx += kThreads) {
             const int r = idx / gpr, c = (idx - r * gpr) * 4;
@@ -92,10 +125,17 @@ __global__ __launch_bounds__(kThreads) void detect_kernel(DetectArgs args)
                 for (int k = 0; k < 4 && c + k < tw; ++k) dst[k] = src[k];
             }
         }
+        }
     }
     __syncthreads();
 
     // ---- level 0: groups of G lanes per window ----
+    // Packed form (first window side a multiple of 4): a lane reads its rows
+    // 4 pixels at a time and keeps 16-bit keys value << 8 | (row count << lc
+    // | column in window), which order its pixels as (value, raster index)
+    // do; two v_perm_b32 build four keys, v_pk_max_u16 / v_pk_min_u16 keep the
+    // extremes and v_sad_u8 adds the four pixels. The lane's extremes are then
+    // expanded to tile keys.
     {
         const int L0 = args.L[0];
         const int n0 = T / L0, nw = n0 * n0;
@@ -103,6 +143,11 @@ __global__ __launch_bounds__(kThreads) void detect_kernel(DetectArgs args)
         while (G < 64 && 2 * G <= L0 && 2 * G * nw <= kThreads) G *= 2;
         const int groups = kThreads / G;
         const int g = tid % G, grp = tid / G;
+        const int rows_pl = (L0 + G - 1) / G;   // rows per lane
+        int lc = 0, rb = 0;
+        while ((1 << lc) < L0) ++lc;
+        while ((1 << rb) < rows_pl) ++rb;
+        const bool packed = (L0 % 4) == 0 && lc + rb <= 8;
         uint32_t* rec = smem + args.lvl_off[0];
         const int nbx = (int)n_windows(I.w, L0);
         for (int wb = 0; wb < nw; wb += groups) {   // uniform trip count for the shuffles
@@ -116,14 +161,51 @@ __global__ __launch_bounds__(kThreads) void detect_kernel(DetectArgs args)
                 c0 = wx * L0;
                 valid = r0 < th && c0 < tw;
                 const int r1 = min(r0 + L0, th), c1 = min(c0 + L0, tw);
-                for (int r = r0 + g; r < r1; r += G) {
-                    const uint8_t* row = pix + r * Tp;
-                    for (int c = c0; c < c1; ++c) {
-                        const uint32_t v = row[c];
-                        const uint32_t key = (v << 16) | ((uint32_t)r << 8) | (uint32_t)c;
-                        kmax = max(kmax, key);
-                        kmin = min(kmin, key);
-                        sum += v;
+                if (packed) {
+                    uint32_t pmax = 0u, pmin = 0xFFFFFFFFu;
+                    int ri = 0;
+                    for (int r = r0 + g; r < r1; r += G, ++ri) {
+                        const uint8_t* row = pix + r * Tp;
+                        uint32_t cbytes = (uint32_t)(ri << lc) * 0x01010101u + 0x03020100u;
+                        int c = c0;
+                        for (; c + 4 <= c1; c += 4, cbytes += 0x04040404u) {
+                            const uint32_t w4 = *reinterpret_cast<const uint32_t*>(row + c);
+                            // keys of columns c, c + 1 and c + 2, c + 3
+                            const uint32_t lo = __builtin_amdgcn_perm(w4, cbytes, 0x05010400u);
+                            const uint32_t hi = __builtin_amdgcn_perm(w4, cbytes, 0x07030602u);
+                            pmax = pk_max(pmax, pk_max(lo, hi));
+                            pmin = pk_min(pmin, pk_min(lo, hi));
+                            sum = __builtin_amdgcn_sad_u8(w4, 0u, sum);
+                        }
+                        for (; c < c1; ++c) {   // the image's ragged right edge
+                            const uint32_t v = row[c];
+                            const uint32_t k = (v << 8) | (uint32_t)((ri << lc) | (c - c0));
+                            pmax = pk_max(pmax, k | (k << 16));
+                            pmin = pk_min(pmin, k | (k << 16));
+                            sum += v;
+                        }
+                    }
+                    if (ri > 0) {   // the lane saw pixels: expand its two keys
+                        const uint32_t km = max(pmax & 0xFFFFu, pmax >> 16);
+                        const uint32_t kn = min(pmin & 0xFFFFu, pmin >> 16);
+                        const uint32_t msk = (1u << lc) - 1u;
+                        kmax = ((km >> 8) << 16) |
+                               ((uint32_t)(r0 + g + (int)((km & 255u) >> lc) * G) << 8) |
+                               (uint32_t)(c0 + (int)(km & msk));
+                        kmin = ((kn >> 8) << 16) |
+                               ((uint32_t)(r0 + g + (int)((kn & 255u) >> lc) * G) << 8) |
+                               (uint32_t)(c0 + (int)(kn & msk));
+                    }
+                } else {
+                    for (int r = r0 + g; r < r1; r += G) {
+                        const uint8_t* row = pix + r * Tp;
+                        for (int c = c0; c < c1; ++c) {
+                            const uint32_t v = row[c];
+                            const uint32_t key = (v << 16) | ((uint32_t)r << 8) | (uint32_t)c;
+                            kmax = max(kmax, key);
+                            kmin = min(kmin, key);
+                            sum += v;
+                        }
                     }
                 }
             }
@@ -340,8 +422,8 @@ int launch_detect(const lpsift_image* imgs, int n, const Geometry& g,
         const int ns = T / g.L[s];
         words += 3 * ns * ns;
     }
-    a.tile_words = words;
-    const size_t lds = (size_t)words * 4 + (size_t)a.Tp * T;
+    a.tile_words = (words + 3) & ~3;   // the pixel tile 16-byte aligned in LDS
+    const size_t lds = (size_t)a.tile_words * 4 + (size_t)a.Tp * T;
     for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
         const int nb = (n - b0 < kMaxBatch) ? n - b0 : kMaxBatch;
         a.n_images = nb;
