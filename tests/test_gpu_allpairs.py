@@ -86,7 +86,7 @@ def check_oracle(tiles, ap, Ls, tile_k, pair_k, n_desc=None, n_query=None, seed=
     check_rule_i(A, B, g)
 
 
-@pytest.mark.parametrize("prec", [0, 3])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_allpairs_graph_replays(gpu, prec):
     import torch
     tiles = small_tiles()
@@ -98,7 +98,8 @@ def test_allpairs_graph_replays(gpu, prec):
     ap.run()
     torch.cuda.synchronize()
     ref = snapshot(ap)
-    check_oracle(tiles, ap, Ls, tile_k=4, pair_k=10)
+    if prec in (0, 3):            # the exact paths; BF16 / FP8 are approximate
+        check_oracle(tiles, ap, Ls, tile_k=4, pair_k=10)
     say("all pairs capture", prec)
     ap.capture()
     torch.cuda.synchronize()
