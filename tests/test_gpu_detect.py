@@ -21,6 +21,8 @@ CASES = [
     (64, 64, [8, 24, 48], 4, 6),
     (480, 640, [16, 32, 64], 1, 7),            # constant image
     (300, 515, [4, 8, 16, 32, 64, 128], 256, 8),
+    (250, 333, [12, 24], 256, 9),             # 120-px tiles, 8-bit packed row/column codes
+    (161, 320, [20, 40, 120], 3, 10),         # first side 20: 5-bit columns
 ]
 
 
