@@ -424,7 +424,7 @@ def bench_learned(args, dev, pairs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(images and match pairs would shard across GPUs with no reduction)",
               file=sys.stderr)
         sys.exit(2)
