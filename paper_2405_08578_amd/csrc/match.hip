@@ -146,18 +146,6 @@ __device__ inline uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
-// Branch-free insertion into a (score, index) top-2; on equal scores the
-// earlier (lower) index stays first because candidates arrive in index order.
-__device__ inline void top2_push(float s, int j, float& s1, int& j1, float& s2, int& j2)
-{
-    const bool lt1 = s < s1;
-    const bool lt2 = s < s2;
-    s2 = lt1 ? s1 : (lt2 ? s : s2);
-    j2 = lt1 ? j1 : (lt2 ? j : j2);
-    s1 = lt1 ? s : s1;
-    j1 = lt1 ? j : j1;
-}
-
 // One (query block, chunk) work item of the FP32 contraction. nq: number of
 // queries; qlist (optional) maps list entry i to its query row, results for
 // entry i are stored at position i.
