@@ -328,7 +328,7 @@ __device__ inline float wave_sum(float v)
 __device__ inline float sqdist(float a0, float a1, const float* __restrict__ B, int64_t j, int lane)
 {
     const float x0 = a0 - B[j * 128 + lane], x1 = a1 - B[j * 128 + 64 + lane];
-    return wave_sum(x0 * x0 + x1 * x1);
+    return wave_sum(fmaf(x0, x0, x1 * x1));
 }
 
 // ordered insert by (squared distance, index)
@@ -354,9 +354,27 @@ __device__ inline void write_result(int64_t q, float e1, int j1, float e2, doubl
     d2out[q] = dd2;
 }
 
-// One wavefront per query: keep the 4 best candidates by contraction score
-// (chunks x 4 entries, up to 256: 4 per lane), recompute their distances
-// directly, then the ratio test.
+// Sixteen lanes per query (four queries per wavefront): keep the 4 best
+// candidates by contraction score (chunks x 4 entries), recompute their
+// distances directly, then the ratio test. Lane t of a group holds elements
+// t + 16 u of a row and adds them in the order of a 64-lane butterfly over
+// pairs (l, l + 64), so distances are bit-identical to the wavefront sums of
+// the other rescoring paths.
+__device__ inline float group_sqdist(const float (&a)[8], const float* __restrict__ b, int t)
+{
+    float p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const float x0 = a[u] - b[t + 16 * u], x1 = a[u + 4] - b[t + 16 * u + 64];
+        p[u] = fmaf(x0, x0, x1 * x1);   // virtual lane t + 16 u
+    }
+    // butterfly levels 32 and 16 within the lane, then 8 .. 1 across the group
+    float v = (p[0] + p[2]) + (p[1] + p[3]);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+    return v;
+}
+
 __device__ inline void rescore_f32_query(const float* __restrict__ A, const float* __restrict__ B,
                                          int chunks, int64_t i, int64_t q,
                                          const int32_t* __restrict__ cidx,
@@ -364,72 +382,52 @@ __device__ inline void rescore_f32_query(const float* __restrict__ A, const floa
                                          float abs_thresh, int32_t* __restrict__ match,
                                          float* __restrict__ d1out, float* __restrict__ d2out)
 {
-    const int lane = threadIdx.x & 63;
-    const int nc = chunks * kKeep;   // <= 256
-    float sc[4];
-    int id[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int e = lane + 64 * k;
-        sc[k] = INFINITY;
-        id[k] = 0x7FFFFFFF;
-        if (e < nc) {
-            const int c = cidx[i * nc + e];
-            if (c >= 0) {
-                id[k] = c;
-                sc[k] = cscore[i * nc + e];
-            }
-        }
-    }
+    const int t = threadIdx.x & 15;
+    const int nc = chunks * kKeep;   // <= 256: up to 16 entries per lane
     // the (up to) 4 best entries by contraction score, selected first ...
     int pick[4];
     int cnt = 0;
+    int taken[4] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
 #pragma unroll
     for (int round = 0; round < 4; ++round) {
-        // this lane's best entry, then the wavefront's
-        float bs = sc[0];
-        int bi = id[0];
-#pragma unroll
-        for (int k = 1; k < 4; ++k)
-            if (sc[k] < bs || (sc[k] == bs && id[k] < bi)) {
-                bs = sc[k];
-                bi = id[k];
+        // this lane's best untaken entry, then the group's
+        float bs = INFINITY;
+        int bi = 0x7FFFFFFF;
+        for (int e = t; e < nc; e += 16) {
+            const int c = cidx[i * nc + e];
+            if (c < 0 || c == taken[0] || c == taken[1] || c == taken[2]) continue;
+            const float sc = cscore[i * nc + e];
+            if (sc < bs || (sc == bs && c < bi)) {
+                bs = sc;
+                bi = c;
             }
+        }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float os = __shfl_xor(bs, off);
-            const int oi = __shfl_xor(bi, off);
+        for (int off = 8; off > 0; off >>= 1) {
+            const float os = __shfl_xor(bs, off, 16);
+            const int oi = __shfl_xor(bi, off, 16);
             if (os < bs || (os == bs && oi < bi)) {
                 bs = os;
                 bi = oi;
             }
         }
         pick[round] = bi;
+        taken[round] = bi;
         if (bi != 0x7FFFFFFF && bs != INFINITY) cnt = round + 1;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (id[k] == bi) sc[k] = INFINITY, id[k] = 0x7FFFFFFF;   // taken (ids are unique)
     }
     // ... then their rows loaded together (one memory latency instead of four)
     // and their distances computed directly; the top-2 by (distance, index)
     // does not depend on the insertion order
-    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
-    float b0[4], b1[4];
+    float a[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        b0[k] = (k < cnt) ? B[(int64_t)pick[k] * 128 + lane] : 0.0f;
-        b1[k] = (k < cnt) ? B[(int64_t)pick[k] * 128 + 64 + lane] : 0.0f;
-    }
+    for (int u = 0; u < 8; ++u) a[u] = A[q * 128 + t + 16 * u];
     float e1 = INFINITY, e2 = INFINITY;
     int j1 = -1, j2 = -1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (k < cnt) {
-            const float x0 = a0 - b0[k], x1 = a1 - b1[k];
-            best2_insert(wave_sum(x0 * x0 + x1 * x1), pick[k], e1, j1, e2, j2);
-        }
+        if (k < cnt) best2_insert(group_sqdist(a, B + (int64_t)pick[k] * 128, t), pick[k], e1, j1, e2, j2);
     }
-    if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
+    if (t == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
 }
 
 // ------------------------------------------------------ low-precision paths --
@@ -738,7 +736,7 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
     for (int k = 0; k < kLpRescore; ++k) {
         if (k < cnt) {
             const float x0 = a0 - b0[k], x1 = a1 - b1[k];
-            best2_insert(wave_sum(x0 * x0 + x1 * x1), (int)pick[k], e1, j1, e2, j2);
+            best2_insert(wave_sum(fmaf(x0, x0, x1 * x1)), (int)pick[k], e1, j1, e2, j2);
         }
     }
     if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
@@ -1201,7 +1199,7 @@ struct RescoreF32Batch {
 __global__ __launch_bounds__(256) void rescore_f32_kernel(const RescoreF32Batch b)
 {
     auto items = [](const RescoreF32Job& J) {
-        return ((J.qlist ? (int64_t)*J.qcount : J.nq) + 3) / 4;
+        return ((J.qlist ? (int64_t)*J.qcount : J.nq) + 15) / 16;
     };
     for (int64_t it = blockIdx.x;; it += gridDim.x) {
         int64_t local;
@@ -1209,7 +1207,7 @@ __global__ __launch_bounds__(256) void rescore_f32_kernel(const RescoreF32Batch 
         if (k < 0) return;
         const RescoreF32Job& J = b.j[k];
         const int64_t nq = J.qlist ? (int64_t)*J.qcount : J.nq;
-        const int64_t i = local * 4 + (threadIdx.x >> 6);
+        const int64_t i = local * 16 + (threadIdx.x >> 4);   // 16 queries per workgroup
         if (i < nq)
             rescore_f32_query(J.A, J.B, J.chunks, i, J.qlist ? J.qlist[i] : i, J.cidx, J.cscore,
                               b.ratio, b.abs_thresh, J.match, J.d1, J.d2);
@@ -1603,7 +1601,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
             if (P.nB == 0) {            // no candidates: every query rejected
                 rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, nullptr, nullptr,
                                              P.match, P.d1, P.d2, P.nA, 0};
-                rf_most += (P.nA + 3) / 4;
+                rf_most += (P.nA + 15) / 16;
                 continue;
             }
             if (lp) {
@@ -1623,7 +1621,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
                 main_wg += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
                 rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, Q.fidx, Q.fscore,
                                              P.match, P.d1, P.d2, P.nA, Q.pf.chunks};
-                rf_most += (P.nA + 3) / 4;
+                rf_most += (P.nA + 15) / 16;
                 continue;
             }
             // split path, then the FP32 re-match of the queries it did not certify
@@ -1639,7 +1637,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
             fall_most += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
             rf.j[rf.n++] = RescoreF32Job{P.A, P.B, Q.fb, Q.cnt, Q.fidx, Q.fscore, P.match, P.d1,
                                          P.d2, P.nA, Q.pf.chunks};
-            rf_most += (P.nA + 3) / 4;
+            rf_most += (P.nA + 15) / 16;
         }
         // the split rows' maxima are accumulated with atomics: zero them first
         if (cnt.n > 0)
