@@ -688,58 +688,71 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
     float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
     float* __restrict__ d2out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nA) return;
-    const int ne = chunks * 2 * K;   // <= 64
-    float sc = INFINITY;
-    int64_t j = -1;
-    if (lane < ne) {
-        const uint32_t key = keys[q * ne + lane];
-        if (key < 0x7F800000u) {
-            sc = __uint_as_float(key & ~idx_mask);
-            j = (int64_t)(lane / (2 * K)) * chunk_len + (key & idx_mask);
+    // 16 lanes per query, four queries per wavefront (see rescore_f32_query)
+    const int t = threadIdx.x & 15;
+    const int64_t q = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (q >= nA) return;   // the whole group of 16 lanes leaves together
+    const int ne = chunks * 2 * K;   // <= 64: up to 4 entries per lane
+    float sc[4];
+    int64_t jv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = t + 16 * u;
+        sc[u] = INFINITY;
+        jv[u] = -1;
+        if (e < ne) {
+            const uint32_t key = keys[q * ne + e];
+            if (key < 0x7F800000u) {
+                sc[u] = __uint_as_float(key & ~idx_mask);
+                jv[u] = (int64_t)(e / (2 * K)) * chunk_len + (key & idx_mask);
+            }
         }
     }
-    // the kLpRescore best kept keys, selected first ...
+    // the kLpRescore best kept keys (ties: lower entry first), selected first ...
     int64_t pick[kLpRescore];
     int cnt = 0;
 #pragma unroll
     for (int round = 0; round < kLpRescore; ++round) {
-        float bs = sc;
-        int bl = lane;
+        float bs = sc[0];
+        int be = t;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float os = __shfl_xor(bs, off);
-            const int ol = __shfl_xor(bl, off);
-            if (os < bs || (os == bs && ol < bl)) {
+        for (int u = 1; u < 4; ++u)
+            if (sc[u] < bs) {   // entries of a lane ascend, so ties keep the lower one
+                bs = sc[u];
+                be = t + 16 * u;
+            }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            const float os = __shfl_xor(bs, off, 16);
+            const int oe = __shfl_xor(be, off, 16);
+            if (os < bs || (os == bs && oe < be)) {
                 bs = os;
-                bl = ol;
+                be = oe;
             }
         }
         if (bs != INFINITY) cnt = round + 1;
-        if (lane == bl) sc = INFINITY;
-        pick[round] = __shfl(j, bl);
+        int64_t jj = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + 16 * u == be) {
+                jj = jv[u];
+                sc[u] = INFINITY;
+            }
+        pick[round] = __shfl(jj, be & 15, 16);
     }
     // ... then their rows loaded together and their distances computed
     // directly; the top-2 by (distance, index) does not depend on the order
-    const float a0 = A[q * 128 + lane], a1 = A[q * 128 + 64 + lane];
-    float b0[kLpRescore], b1[kLpRescore];
+    float a[8];
 #pragma unroll
-    for (int k = 0; k < kLpRescore; ++k) {
-        b0[k] = (k < cnt) ? B[pick[k] * 128 + lane] : 0.0f;
-        b1[k] = (k < cnt) ? B[pick[k] * 128 + 64 + lane] : 0.0f;
-    }
+    for (int u = 0; u < 8; ++u) a[u] = A[q * 128 + t + 16 * u];
     float e1 = INFINITY, e2 = INFINITY;
     int j1 = -1, j2 = -1;
 #pragma unroll
     for (int k = 0; k < kLpRescore; ++k) {
-        if (k < cnt) {
-            const float x0 = a0 - b0[k], x1 = a1 - b1[k];
-            best2_insert(wave_sum(fmaf(x0, x0, x1 * x1)), (int)pick[k], e1, j1, e2, j2);
-        }
+        if (k < cnt)
+            best2_insert(group_sqdist(a, B + pick[k] * 128, t), (int)pick[k], e1, j1, e2, j2);
     }
-    if (lane == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
+    if (t == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
 }
 
 // ------------------------------------------------------------- BF16x3 path --
@@ -1450,7 +1463,7 @@ int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStre
     const float* B = io.B;
     char* base = static_cast<char*>(io.ws);
     const MatchPlan p = plan_match(nA, nB, mp);
-    const dim3 gr((unsigned)((nA + 3) / 4));
+    const dim3 gr((unsigned)((nA + 15) / 16));   // rescore: 16 queries per workgroup
     const WsLp L = ws_lp(nA, nB, mp->precision, p);
     float* scal = reinterpret_cast<float*>(base + L.scal);
     uint32_t* counters = reinterpret_cast<uint32_t*>(scal);   // [1], [2] max bits
