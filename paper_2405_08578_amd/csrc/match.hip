@@ -1171,26 +1171,27 @@ __device__ inline int64_t f32_queries(const F32Job& J)
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup w on XCD
-// w % 8), each XCD with its own L2. With a grid that is a multiple of
-// kXcdBlock, the items are taken in blocks of kXcdBlock = 8 x kXcdRun: in
-// each block, the workgroups of XCD x take the run of kXcdRun consecutive
-// (chunk, query block) items starting at x * kXcdRun, so the workgroups of
-// one XCD stream the same candidate chunk through their L2 instead of every
-// chunk, while successive blocks keep the XCDs' shares of uneven jobs even
-// (same items, same results; only the order).
+// w % 8), each XCD with its own L2. With a grid that is a multiple of 8, the
+// N items are taken in blocks of 8 x run, run = min(kXcdRun, ceil(N / 8)):
+// in each block, the workgroups of XCD x take the run consecutive (chunk,
+// query block) items starting at x * run, so the workgroups of one XCD stream
+// the same candidate chunk through their L2 instead of every chunk, small
+// launches still spread over all XCDs, and successive blocks keep the XCDs'
+// shares of uneven jobs even (same items, same results; only the order).
 constexpr int kXcdRun = 64;
-constexpr int kXcdBlock = 8 * kXcdRun;
 
 __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(const F32Batch b)
 {
     auto items = [](const F32Job& J) { return (f32_queries(J) + kQB - 1) / kQB * J.chunks; };
     int64_t n_items = 0;
     for (int k = 0; k < b.n; ++k) n_items += items(b.j[k]);
-    const bool by_xcd = (gridDim.x % (unsigned)kXcdBlock) == 0;
-    const int64_t n_virtual = by_xcd ? (n_items + kXcdBlock - 1) / kXcdBlock * kXcdBlock : n_items;
+    const bool by_xcd = (gridDim.x % 8u) == 0;
+    const int64_t run = (n_items + 7) / 8 < kXcdRun ? ((n_items + 7) / 8 > 0 ? (n_items + 7) / 8 : 1)
+                                                    : kXcdRun;
+    const int64_t blk = 8 * run;
+    const int64_t n_virtual = by_xcd ? (n_items + blk - 1) / blk * blk : n_items;
     for (int64_t v = blockIdx.x; v < n_virtual; v += gridDim.x) {
-        const int64_t it = by_xcd ? (v / kXcdBlock) * kXcdBlock + (v % 8) * kXcdRun + (v / 8) % kXcdRun
-                                  : v;
+        const int64_t it = by_xcd ? (v / blk) * blk + (v % 8) * run + (v / 8) % run : v;
         if (it >= n_items) continue;   // uniform over the workgroup
         int64_t local;
         const int k = find_job(b, it, items, local);
@@ -1679,9 +1680,8 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
         }
         if (main.n > 0) {
             TimedScope ts(LPSIFT_KERNEL_MATCH_FP32, stream);
-            // a multiple of kXcdBlock workgroups: the XCD-ordered item mapping
-            hipLaunchKernelGGL(match_topk_f32_kernel,
-                               dim3((unsigned)((main_wg + kXcdBlock - 1) / kXcdBlock * kXcdBlock)), dim3(256), 0,
+            // a multiple of 8 workgroups: the XCD-ordered item mapping
+            hipLaunchKernelGGL(match_topk_f32_kernel, dim3((unsigned)((main_wg + 7) / 8 * 8)), dim3(256), 0,
                                stream, main);
         }
         if (x3.n > 0) {
