@@ -1171,21 +1171,24 @@ __device__ inline int64_t f32_queries(const F32Job& J)
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup w on XCD
-// w % 8), each XCD with its own L2. With a grid that is a multiple of 8, the
-// N items are taken in blocks of 8 x run, run = min(kXcdRun, ceil(N / 8)):
-// in each block, the workgroups of XCD x take the run consecutive (chunk,
-// query block) items starting at x * run, so the workgroups of one XCD stream
-// the same candidate chunk through their L2 instead of every chunk, small
-// launches still spread over all XCDs, and successive blocks keep the XCDs'
-// shares of uneven jobs even (same items, same results; only the order).
+// w % 8), each XCD with its own L2. When all N items run in one wave (at most
+// kOneWave workgroups, 2 per CU) and the grid is a multiple of 8, they are
+// taken in blocks of 8 x run, run = min(kXcdRun, ceil(N / 8)): in each block
+// the workgroups of XCD x take the run consecutive (chunk, query block)
+// items starting at x * run, so one XCD streams one candidate chunk through
+// its L2 instead of every chunk, and small launches still spread over all
+// XCDs (same items, same results; only the order). Launches of many waves
+// (batched pairs with smaller chunks) keep the launch order, which measured
+// faster there.
 constexpr int kXcdRun = 64;
+constexpr int64_t kOneWave = 512;
 
 __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(const F32Batch b)
 {
     auto items = [](const F32Job& J) { return (f32_queries(J) + kQB - 1) / kQB * J.chunks; };
     int64_t n_items = 0;
     for (int k = 0; k < b.n; ++k) n_items += items(b.j[k]);
-    const bool by_xcd = (gridDim.x % 8u) == 0;
+    const bool by_xcd = (gridDim.x % 8u) == 0 && n_items <= kOneWave;
     const int64_t run = (n_items + 7) / 8 < kXcdRun ? ((n_items + 7) / 8 > 0 ? (n_items + 7) / 8 : 1)
                                                     : kXcdRun;
     const int64_t blk = 8 * run;
