@@ -679,7 +679,7 @@ __global__ __launch_bounds__(256, 1) void match_topk_lp_kernel(
     }
 }
 
-// One wavefront per query. Entries: K keys per (chunk, lane half). The 8
+// 16 lanes per query. Entries: K keys per (chunk, lane half). The 8
 // smallest kept keys are rescored in FP32 (approximate paths).
 template <int K>
 __global__ __launch_bounds__(256) void rescore_lp_kernel(
@@ -1209,7 +1209,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(const F32Batch b
     }
 }
 
-// FP32 rescore, one wavefront per query (list entry). chunks = 0: no
+// FP32 rescore, 16 lanes per query (list entry). chunks = 0: no
 // candidates (an empty candidate set), every query is rejected.
 struct RescoreF32Job {
     const float* A;
