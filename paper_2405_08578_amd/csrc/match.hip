@@ -833,6 +833,12 @@ __device__ inline uint4 load_split8(const float* p, uint4& lo)
 // Padded candidate rows start their accumulator here instead of -|b|^2/2: a
 // finite value far below any real score (keys stay free of inf and NaN).
 constexpr float kX3Pad = -3.0e38f;
+// k1's update is med3(x, k1, kX3Top), which is max(x, k1) for every key below
+// kX3Top: a key is a.b - |b|^2/2 <= |a|^2/2, so any pair of descriptors whose
+// squared norms are finite in FP32 stays below it. A plain max would first
+// quiet x as a possible NaN, since x is rebuilt from integer bits: one more
+// VALU instruction per accumulator in the loop.
+constexpr float kX3Top = 3.0e38f;
 
 __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
                                     const uint8_t* __restrict__ Bhl, int64_t nB,
@@ -951,7 +957,7 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
                 const float x = __int_as_float((__float_as_int(acc[t][r]) & -16) | r);
                 k3[t] = __builtin_amdgcn_fmed3f(x, k2[t], k3[t]);   // k1 >= k2 >= k3
                 k2[t] = __builtin_amdgcn_fmed3f(x, k1[t], k2[t]);
-                k1[t] = fmaxf(x, k1[t]);
+                k1[t] = __builtin_amdgcn_fmed3f(x, k1[t], kX3Top);
             }
         }
         // tile of each kept key, as in the FP32 path: a key bit-equal to its
