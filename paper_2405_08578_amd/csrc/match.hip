@@ -875,7 +875,7 @@ __device__ inline void topk_x3_item(const float* __restrict__ A, int64_t nA,
     // Per lane and query set: the two largest keys and the third largest. A
     // key is the float acc with its low 4 bits replaced by the accumulator row
     // r (a change of at most 15 units in the last place, which the rescoring
-    // bound allows for), kept with v_max_f32 / v_med3_f32; the tile of each
+    // bound allows for), kept with three v_med3_f32; the tile of each
     // kept key is recovered once per tile by comparing it with its value
     // before the tile.
     float k1[2], k2[2], k3[2];
