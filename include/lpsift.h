@@ -132,7 +132,10 @@ typedef struct lpsift_keypoints {
  *                  term, FP32 accumulation), certified per query by an error
  *                  bound; queries it cannot certify are re-matched with
  *                  precision 0, so the lists equal precision 0's.
- *  b_chunks    candidate-range split of the contraction (0 = automatic, <= 16)
+ *              Every precision expects descriptors whose squared norms are
+ *              finite in FP32 (true of every row lpsift_describe writes);
+ *              for other inputs the lists are unspecified.
+ *  b_chunks   candidate-range split of the contraction (0 = automatic, <= 16)
  *  stats       optional device pointer to one uint32: after the call (stream
  *              order) it holds the number of queries, summed over all pairs,
  *              that precision 3 re-matched with precision 0 (0 otherwise) */
