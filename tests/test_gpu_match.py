@@ -99,6 +99,39 @@ def test_match_identical_candidates_in_two_tiles(gpu, precision, pos):
     assert np.array_equal(g["match"][1:], o["match"][1:])
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+def test_match_zero_rows(gpu, precision):
+    # Keypoints on the image border get all-zero descriptors, so real sets hold
+    # many zero rows: here among the candidates (several in one 32-row tile,
+    # some at the same row of different tiles) and among the queries. A zero
+    # candidate scores exactly 0 in the contraction (keys of magnitude below
+    # the smallest normal float). A zero query's two nearest are zero
+    # candidates at distance exactly 0: a tie, rejected. Every other query
+    # follows the oracle (exact paths) or the FP32 path (BF16, FP8).
+    rng = np.random.Generator(np.random.PCG64(41))
+    nA, nB = 400, 700
+    B = synth.random_unit_rows(nB, 128, rng).astype(np.float32)
+    zb = np.unique(np.concatenate([rng.choice(nB, 60, replace=False), [3, 5, 7, 35, 67, 99]]))
+    B[zb] = 0.0
+    live = np.setdiff1d(np.arange(nB), zb)
+    A = synth.noisy_copies(B.astype(np.float64), rng.choice(live, nA), 0.03, rng).astype(np.float32)
+    za = rng.choice(nA, 40, replace=False)
+    A[za] = 0.0
+    say("zero rows", precision)
+    g = run_match(gpu, A, B, precision=precision)
+    assert np.all(g["match"][za] == -1)
+    assert np.all(g["d1"][za] == 0.0) and np.all(g["d2"][za] == 0.0)
+    if precision in (0, 3):
+        check_rule_i(A, B, g)
+    else:
+        nz = np.setdiff1d(np.arange(nA), za)
+        g32 = run_match(gpu, A, B, precision=0)
+        j1_same = g["match"][nz] == g32["match"][nz]
+        assert j1_same.mean() > 0.97
+        both = (g["match"][nz] >= 0) & j1_same
+        assert np.array_equal(g["d1"][nz][both], g32["d1"][nz][both])
+
+
 @pytest.mark.parametrize("precision", [0, 3])
 @pytest.mark.parametrize("scale,seed", [(1e-3, 31), (1.0, 32), (1e3, 33)])
 def test_match_signed_scaled_sets(gpu, precision, scale, seed):
