@@ -522,8 +522,13 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* __restrict__
 // keys[((i * chunks + chunk) * 2 + h) * K + {0 .. K-1}] = lane half h's best K
 // keys of query i, ascending (0xFFFFFFFF = none). key = (float bits of score & ~idx_mask) | index
 // in chunk, score = |b|^2 + C - 2 a.b > 0 (C from the per-call scalars).
+// Two workgroups per CU: within the 256 registers a lane then has, the
+// accumulators are ordinary VGPRs that the epilogue reads directly (with
+// more registers the compiler places them in AGPRs, and every score costs
+// one more v_accvgpr_read), and the two 32-row halves of a tile run one
+// after the other so that only one half's accumulators are live.
 template <int P, int K>
-__global__ __launch_bounds__(256, 1) void match_topk_lp_kernel(
+__global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
     const uint8_t* __restrict__ Aq, const float* __restrict__ sA, int64_t nA,
     const uint8_t* __restrict__ Bq, const float* __restrict__ sB, int64_t nB,
     const float* __restrict__ nrmB, const float* __restrict__ scal, int64_t chunk_len,
@@ -600,7 +605,7 @@ __global__ __launch_bounds__(256, 1) void match_topk_lp_kernel(
         if (t0 + kLpCT < ce) fetch(t0 + kLpCT);
         const uint32_t local0 = (uint32_t)(t0 - cb);
 
-#pragma unroll
+#pragma unroll 1
         for (int sub = 0; sub < kLpCT / 32; ++sub) {
             floatx16 acc[kLpSets];
 #pragma unroll
