@@ -314,6 +314,24 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
                  void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                  float* const* d2, void* stream);
 
+/* The reduced-precision forms of descriptors that lpsift_match contracts at
+ * precision 1 and 2 (a precision variant of the Sec. 2.4 contraction; the
+ * matcher runs this same quantisation on its inputs):
+ *  precision 1  q = uint16 [n][128]: the BF16 bits of each FP32 element,
+ *               rounded to nearest even; scale unused (may be null).
+ *  precision 2  q = uint8 [n][128]: FP8 E4M3 (OCP: bias 7, largest finite
+ *               448, subnormals kept) bytes of v * fl(448 / m), where
+ *               m = max_k |desc[i][k]| in FP32 and the product is an FP32
+ *               product clamped to [-448, 448] before rounding to nearest
+ *               even; scale[i] = fl(m / 448) (FP32), or 1 for a zero row, so
+ *               that desc[i] ~ scale[i] * q[i].
+ * desc 16-byte aligned; q 16-byte (precision 1) or 8-byte (precision 2)
+ * aligned; scale 4-byte aligned. Caller-owned buffers, written in stream
+ * order. Errors: EINVAL (bad precision, n < 0, null or misaligned pointer),
+ * EHIP. */
+int lpsift_quantize_lowp(const float* desc, int64_t n, int32_t precision, void* q, float* scale,
+                         void* stream);
+
 /* Autotuner of the candidate-range split of lpsift_match (its b_chunks): for
  * each of n_candidates values (each 1..16) it runs the call once untimed and
  * reps times timed on `stream`, stores the mean milliseconds per call in

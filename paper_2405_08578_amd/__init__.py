@@ -64,7 +64,8 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_ransac_workspace_size", "lpsift_ransac", "lpsift_quantize_u8",
            "lpsift_match_u8_workspace_size", "lpsift_match_u8",
            "lpsift_describe_multi_workspace_size", "lpsift_describe_multi",
-           "lpsift_warp_blend", "lpsift_probe_out_size", "lpsift_probe_ops", "lpsift_probe")
+           "lpsift_warp_blend", "lpsift_probe_out_size", "lpsift_probe_ops", "lpsift_probe",
+           "lpsift_quantize_lowp")
 
 _lib = None
 
@@ -139,6 +140,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                   P(c_vp), P(c_vp), P(c_vp), c_vp, c_vp, c_vp]
     lib.lpsift_quantize_u8.restype = ctypes.c_int
     lib.lpsift_quantize_u8.argtypes = [c_vp, c_i64, c_vp, c_vp]
+    lib.lpsift_quantize_lowp.restype = ctypes.c_int
+    lib.lpsift_quantize_lowp.argtypes = [c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]
     lib.lpsift_match_u8_workspace_size.restype = ctypes.c_size_t
     lib.lpsift_match_u8_workspace_size.argtypes = [c_i64, c_i64]
     lib.lpsift_match_u8.restype = ctypes.c_int
@@ -363,6 +366,29 @@ def quantize_u8(desc, out=None, stream=None):
     _check("lpsift_quantize_u8", load().lpsift_quantize_u8(desc.data_ptr(), desc.shape[0],
                                                            out.data_ptr(), _stream(stream)))
     return out
+
+
+def quantize_lowp(desc, precision: int, out=None, scale=None, stream=None):
+    """The BF16 (precision 1: int16 bit patterns [n, 128]) or FP8 E4M3
+    (precision 2: uint8 codes [n, 128] plus FP32 scales [n]) form of
+    descriptors that lpsift_match contracts at that precision. Returns
+    (codes, scales or None)."""
+    import torch
+    if desc.dtype != torch.float32 or desc.dim() != 2 or desc.shape[1] != DESC_DIM \
+            or not desc.is_cuda or not desc.is_contiguous():
+        raise ValueError("descriptors must be contiguous float32 CUDA tensors [n, 128]")
+    if precision not in (1, 2):
+        raise ValueError("precision must be 1 (BF16) or 2 (FP8 E4M3)")
+    n = desc.shape[0]
+    if out is None:
+        out = torch.empty((n, DESC_DIM), dtype=torch.int16 if precision == 1 else torch.uint8,
+                          device=desc.device)
+    if precision == 2 and scale is None:
+        scale = torch.empty(n, dtype=torch.float32, device=desc.device)
+    _check("lpsift_quantize_lowp", load().lpsift_quantize_lowp(
+        desc.data_ptr(), n, precision, out.data_ptr(),
+        scale.data_ptr() if precision == 2 else None, _stream(stream)))
+    return out, (scale if precision == 2 else None)
 
 
 def match_u8_workspace_size(nA: int, nB: int) -> int:

@@ -404,6 +404,19 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
     return launch_match_pairs(io.data(), n_pairs, mp, static_cast<hipStream_t>(stream));
 }
 
+int lpsift_quantize_lowp(const float* desc, int64_t n, int32_t precision, void* q, float* scale,
+                        void* stream)
+{
+    if (n < 0 || n > INT32_MAX) return LPSIFT_EINVAL;
+    if (precision != 1 && precision != 2) return LPSIFT_EINVAL;
+    if (n > 0 && (!desc || !q || (precision == 2 && !scale))) return LPSIFT_EINVAL;
+    const uintptr_t qa = reinterpret_cast<uintptr_t>(q);
+    if ((reinterpret_cast<uintptr_t>(desc) & 15u) || (qa & (precision == 1 ? 15u : 7u)) ||
+        (reinterpret_cast<uintptr_t>(scale) & 3u))
+        return LPSIFT_EINVAL;
+    return launch_quantize_lowp(desc, n, precision, q, scale, static_cast<hipStream_t>(stream));
+}
+
 int lpsift_quantize_u8(const float* desc, int64_t n, uint8_t* q, void* stream)
 {
     if (n < 0 || n > INT32_MAX) return LPSIFT_EINVAL;

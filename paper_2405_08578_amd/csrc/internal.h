@@ -110,6 +110,10 @@ struct MatchPlan {
 };
 MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp);
 size_t match_workspace_bytes(int64_t nA, int64_t nB, const lpsift_match_params* mp);
+// The quantised forms the precision 1 / 2 contractions read (the same kernel):
+// BF16 bits [n][128] (precision 1) or E4M3 bytes [n][128] and scales [n] (2).
+int launch_quantize_lowp(const float* desc, int64_t n, int precision, void* q, float* scale,
+                         hipStream_t stream);
 
 // One pair of a match call: descriptor sets, its 256-byte aligned workspace
 // slice of match_workspace_bytes(nA, nB), and its outputs.

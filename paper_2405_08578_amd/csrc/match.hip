@@ -1458,6 +1458,21 @@ MatchPlan plan_fallback(int64_t nA, int64_t nB)
 
 }  // namespace
 
+int launch_quantize_lowp(const float* desc, int64_t n, int precision, void* q, float* scale,
+                         hipStream_t stream)
+{
+    if (n == 0) return LPSIFT_OK;
+    const dim3 grid((unsigned)((n + 15) / 16));
+    uint8_t* y = static_cast<uint8_t*>(q);
+    if (precision == 1)
+        hipLaunchKernelGGL(quantize_kernel<1>, grid, dim3(256), 0, stream, desc, n, y, scale,
+                           (uint32_t*)nullptr);
+    else
+        hipLaunchKernelGGL(quantize_kernel<2>, grid, dim3(256), 0, stream, desc, n, y, scale,
+                           (uint32_t*)nullptr);
+    return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
+}
+
 MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp)
 {
     switch (mp->precision) {

@@ -282,6 +282,23 @@ def test_ransac_gpu_validation(lib):
     assert call(nq=-5) == lp.LPSIFT_EINVAL
 
 
+def test_quantize_lowp_validation(lib):
+    A = ctypes.c_void_p(1 << 20)                 # never dereferenced: every call below fails first
+    S = ctypes.c_void_p(1 << 22)
+    E = lp.LPSIFT_EINVAL
+    q = lib.lpsift_quantize_lowp
+    assert q(A, 4, 0, A, S, None) == E                              # bad precision
+    assert q(A, 4, 3, A, S, None) == E
+    assert q(A, -1, 1, A, None, None) == E
+    assert q(None, 4, 1, A, None, None) == E
+    assert q(A, 4, 2, A, None, None) == E                           # FP8 needs scales
+    assert q(ctypes.c_void_p((1 << 20) + 4), 4, 1, A, None, None) == E
+    assert q(A, 4, 1, ctypes.c_void_p((1 << 20) + 8), None, None) == E   # BF16 rows: 16 B
+    assert q(A, 4, 2, ctypes.c_void_p((1 << 20) + 4), S, None) == E      # FP8 rows: 8 B
+    assert q(A, 4, 2, A, ctypes.c_void_p((1 << 22) + 2), None) == E
+    assert q(None, 0, 1, None, None, None) == lp.LPSIFT_OK           # nothing to do
+
+
 def test_u8_entry_validation(lib):
     A = ctypes.c_void_p(1 << 20)                 # never dereferenced: every call below fails first
     ws = ctypes.c_void_p(1 << 21)
