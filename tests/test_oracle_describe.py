@@ -71,6 +71,100 @@ def test_orientation_two_bin_spike_closed_form():
     assert math.degrees(th[0]) == pytest.approx((k - a1 / (2 * a2)) * 10, abs=1e-9)
 
 
+def roof(g_right, g_left, x0, n=96, c0=40):
+    """I = c0 + g_right (x - x0) right of column x0 and c0 + g_left (x0 - x)
+    left of it: central differences give magnitude 2 g_right at angle 0
+    (bin 0) for x > x0, 2 g_left at angle 180 degrees (bin 18) for x < x0,
+    and |g_right - g_left| at x = x0 (bin 0 or 18 by its sign)."""
+    xx = np.arange(n)
+    row = np.where(xx >= x0, c0 + g_right * (xx - x0), c0 + g_left * (x0 - xx))
+    img = np.tile(row, (n, 1))
+    assert img.min() >= 0 and img.max() <= 255
+    return img.astype(np.uint8)
+
+
+def disc_column_mass(dx, R, sigma):
+    """Sum over the integer offsets (dx, dy) of the disc dx^2 + dy^2 <= R^2 of
+    exp(-(dx^2 + dy^2) / (2 sigma^2)): one column of the Gaussian disc."""
+    if dx * dx > R * R:
+        return 0.0
+    h = math.isqrt(R * R - dx * dx)
+    dy = np.arange(-h, h + 1)
+    return float(np.exp(-(dx * dx + dy * dy) / (2 * sigma * sigma)).sum())
+
+
+def roof_histogram(ws, delta, g_right, g_left, sigma=None, R=None):
+    """Smoothed 36-bin orientation histogram of the roof image at a keypoint
+    delta columns right of the ridge, from geometry alone: each disc column
+    votes its Gaussian mass times its gradient magnitude into bin 0 or 18.
+    Default reading: sigma = w_s / 2, disc radius round(1.5 w_s)."""
+    sigma = 0.5 * ws if sigma is None else sigma
+    R = int(math.floor(1.5 * ws + 0.5)) if R is None else R
+    raw = np.zeros(36)
+    for dx in range(-R, R + 1):
+        col = delta + dx                 # column relative to the ridge
+        if col > 0:
+            mag, b = 2.0 * g_right, 0
+        elif col < 0:
+            mag, b = 2.0 * g_left, 18
+        else:
+            mag, b = abs(g_right - g_left), (0 if g_right > g_left else 18)
+        raw[b] += mag * disc_column_mass(dx, R, sigma)
+    kern = np.array([1, 4, 6, 4, 1]) / 16
+    return np.array([sum(kern[j] * raw[(b + j - 2) % 36] for j in range(5)) for b in range(36)])
+
+
+@pytest.mark.parametrize("ws", [4.0, math.sqrt(32), 8.0, math.sqrt(128)])
+@pytest.mark.parametrize("delta", [0, 1, 3, 6])
+def test_orientation_spatial_weighting_absolute(ws, delta):
+    """The histogram's absolute bin masses pin the Gaussian width (sigma_o =
+    w_s / 2) and the disc radius (round(1.5 w_s)) of the orientation step: a
+    roof image splits the disc at a known column, and the two bins receive
+    the Gaussian mass of their part of the disc. A width or radius one step
+    off changes the masses far beyond rounding (checked below)."""
+    x0, ky = 48, 48
+    img = roof(1, 3, x0)
+    th, hist = oracle.orientation(img, [x0 + delta], [ky], [ws], return_hist=True)
+    want = roof_histogram(ws, delta, 1, 3)
+    assert np.allclose(hist[0], want, rtol=1e-12, atol=1e-12)
+    # theta0: the heavier of the two symmetric peaks, exactly at its bin centre
+    if abs(want[0] - want[18]) > 1e-9 * want.max():
+        exp_deg = 0.0 if want[0] > want[18] else 180.0
+        got = math.degrees(th[0]) % 360.0
+        assert min(abs(got - exp_deg), 360 - abs(got - exp_deg)) < 1e-9
+    # the pin separates the reading from nearby alternatives
+    R = int(math.floor(1.5 * ws + 0.5))
+    for alt in (roof_histogram(ws, delta, 1, 3, sigma=ws), roof_histogram(ws, delta, 1, 3,
+                sigma=ws / 3), roof_histogram(ws, delta, 1, 3, R=R - 1),
+                roof_histogram(ws, delta, 1, 3, R=R + 1)):
+        assert np.max(np.abs(alt - want)) > 1e-4 * want.max()
+
+
+def test_orientation_spatial_weighting_decides_theta():
+    """With the keypoint right of the ridge and the steeper side on the left,
+    which side wins depends on how fast the Gaussian falls off: at w_s = 8
+    (sigma 4, radius 12) the left side's larger gradient outweighs its smaller
+    area for small offsets and loses for larger ones. The switch offset from
+    geometry alone must equal the oracle's."""
+    ws = 8.0
+    x0 = 48
+    img = roof(1, 3, x0)
+    switch = None
+    for delta in range(0, 12):
+        want = roof_histogram(ws, delta, 1, 3)
+        th = oracle.orientation(img, [x0 + delta], [48], [ws])[0]
+        side = 0.0 if want[0] > want[18] else 180.0
+        got = math.degrees(th) % 360.0
+        assert min(abs(got - side), 360 - abs(got - side)) < 1e-9, delta
+        if side == 0.0 and switch is None:
+            switch = delta
+    assert switch is not None and switch > 0
+    # a wider Gaussian (sigma = w_s) would move the switch
+    alt = next(d for d in range(0, 12) if (lambda h: h[0] > h[18])(
+        roof_histogram(ws, d, 1, 3, sigma=ws)))
+    assert alt != switch
+
+
 def separable_spatial(ws, d=4):
     """Per-axis sums of Gaussian x triangle weights: for theta0 = 0 and a
     constant gradient the descriptor mass of cell (cy, cx) is S[cy] S[cx]."""
