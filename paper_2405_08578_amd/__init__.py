@@ -212,6 +212,17 @@ def _stream(stream) -> int:
     return s.cuda_stream
 
 
+def _temp(nbytes: int, dtype, dev, stream):
+    """A temporary device buffer used by work enqueued on `stream`: when that
+    is not the current stream the block is recorded on it, so that the
+    caching allocator does not hand it out again before that work ends."""
+    import torch
+    t = torch.empty(nbytes, dtype=dtype, device=dev)
+    if stream is not None and stream != torch.cuda.current_stream(dev):
+        t.record_stream(stream)
+    return t
+
+
 def _image(t) -> lpsift_image:
     import torch
     if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.dim() != 2 or not t.is_cuda:
@@ -290,7 +301,7 @@ def describe(images, kps, params: Params, workspace=None, theta=None, desc=None,
     p = params.c()
     need = int(lib.lpsift_describe_workspace_size(imgs, n, ctypes.byref(p)))
     if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        workspace = _temp(max(need, 1), torch.uint8, dev, stream)
     th = (c_vp * n)(*[t.data_ptr() for t in theta])
     de = (c_vp * n)(*[t.data_ptr() for t in desc])
     _check("lpsift_describe", lib.lpsift_describe(imgs, n, _kps(kps), ctypes.byref(p),
@@ -316,7 +327,9 @@ def match_workspace_size(nA: Sequence[int], nB: Sequence[int], mp: lpsift_match_
                                                   ctypes.byref(mp)))
 
 
-def _match_args(descA, descB, out, workspace, need):
+def _match_args(descA, descB, out, workspace, need, stream=None):
+    """Pointer arrays of a match call; a missing workspace (when `need` is
+    given) or output is allocated here and tied to `stream`."""
     import torch
     n = len(descA)
     if len(descB) != n or n < 1:
@@ -328,15 +341,16 @@ def _match_args(descA, descB, out, workspace, need):
     dev = descA[0].device
     nA = [int(t.shape[0]) for t in descA]
     nB = [int(t.shape[0]) for t in descB]
-    if workspace is None:
-        workspace = torch.empty(max(need(nA, nB), 256), dtype=torch.uint8, device=dev)
+    if workspace is None and need is not None:
+        workspace = _temp(max(need(nA, nB), 256), torch.uint8, dev, stream)
     if out is None:
         out = [{"match": torch.empty(a, dtype=torch.int32, device=dev),
                 "d1": torch.empty(a, dtype=torch.float32, device=dev),
                 "d2": torch.empty(a, dtype=torch.float32, device=dev)} for a in nA]
     ptr = lambda ts: (c_vp * n)(*[t.data_ptr() for t in ts])
     head = (ptr(descA), (c_i64 * n)(*nA), ptr(descB), (c_i64 * n)(*nB), n)
-    tail = (workspace.data_ptr(), workspace.numel(), ptr([o["match"] for o in out]),
+    tail = (0 if workspace is None else workspace.data_ptr(),
+            0 if workspace is None else workspace.numel(), ptr([o["match"] for o in out]),
             ptr([o["d1"] for o in out]), ptr([o["d2"] for o in out]))
     return out, head, tail
 
@@ -350,7 +364,7 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
     lib = load()
     mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
     out, head, tail = _match_args(descA, descB, out, workspace,
-                                  lambda nA, nB: match_workspace_size(nA, nB, mp))
+                                  lambda nA, nB: match_workspace_size(nA, nB, mp), stream)
     _check("lpsift_match", lib.lpsift_match(*head, ctypes.byref(mp), *tail, _stream(stream)))
     return out
 
@@ -408,8 +422,7 @@ def match_u8(qA, qB, ratio: float = 0.8, abs_thresh: float = math.inf, workspace
     nA, nB = int(qA.shape[0]), int(qB.shape[0])
     dev = qA.device
     if workspace is None:
-        workspace = torch.empty(max(match_u8_workspace_size(nA, nB), 256), dtype=torch.uint8,
-                                device=dev)
+        workspace = _temp(max(match_u8_workspace_size(nA, nB), 256), torch.uint8, dev, stream)
     if out is None:
         out = {"match": torch.empty(nA, dtype=torch.int32, device=dev),
                "d1": torch.empty(nA, dtype=torch.float32, device=dev),
@@ -462,7 +475,7 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
             m.b_chunks = int(c)
             b = max(b, match_workspace_size(nA, nB, m))
         return b
-    _, head, tail = _match_args(descA, descB, None, None, need)
+    _, head, tail = _match_args(descA, descB, None, None, need, stream)
     k = len(candidates)
     ms = (c_f32 * k)()
     best = c_i32(0)
@@ -506,7 +519,7 @@ def describe_selected(images, kps, params: Params, sel, workspace=None, theta=No
     p = params.c()
     need = int(lib.lpsift_describe_workspace_size(imgs, n, ctypes.byref(p)))
     if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        workspace = _temp(max(need, 1), torch.uint8, dev, stream)
     _check("lpsift_describe_selected", lib.lpsift_describe_selected(
         imgs, n, _kps(kps), ctypes.byref(p), (c_vp * n)(*[s.data_ptr() for s in sel]),
         (c_i64 * n)(*ns), workspace.data_ptr(), workspace.numel(),
@@ -533,8 +546,8 @@ def describe_multi(images, kps, params: Params, max_orient: int = 4, peak_ratio:
     P = params.c()
     dev = images[0].device
     if workspace is None:
-        workspace = torch.empty(max(describe_multi_workspace_size(images, params), 256),
-                                dtype=torch.uint8, device=dev)
+        workspace = _temp(max(describe_multi_workspace_size(images, params), 256), torch.uint8,
+                          dev, stream)
     if out is None:
         caps = [int(k["x"].numel()) * max_orient for k in kps]
         out = {"rows": [torch.empty(c, dtype=torch.int32, device=dev) for c in caps],
@@ -675,7 +688,7 @@ def ransac_gpu(kpA, kpB, matches, uniforms, thresh: float = 3.0, selA=None, selB
     rp.uniforms = uniforms.data_ptr()
     need = int(lib.lpsift_ransac_workspace_size((c_i64 * n)(*nq), n, rp.n_iter))
     if workspace is None:
-        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        workspace = _temp(max(need, 256), torch.uint8, dev, stream)
     if out is None:
         out = {"slotA": [torch.empty(q, dtype=torch.int32, device=dev) for q in nq],
                "slotB": [torch.empty(q, dtype=torch.int32, device=dev) for q in nq],
