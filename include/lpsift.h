@@ -10,7 +10,9 @@
  *
  * Conventions shared by every call:
  *  - Pointers are DEVICE pointers unless the comment says "host".
- *  - The caller owns every buffer; the library never allocates device memory.
+ *  - The caller owns every buffer; the library never allocates device memory
+ *    (the one fixed array of lpsift_match_noalloc is placed by the runtime
+ *    when the library's code loads on a device).
  *  - Every call validates all arguments on the host first and returns
  *    LPSIFT_EINVAL / LPSIFT_ECAPACITY / LPSIFT_EUNSUPPORTED without touching the
  *    GPU. Valid calls enqueue kernels on `stream` (a hipStream_t; NULL is the
@@ -313,6 +315,31 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
                  const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
                  void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                  float* const* d2, void* stream);
+
+/* lpsift_match without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The workspace is a fixed array of
+ * LPSIFT_NOALLOC_SCRATCH_BYTES inside the library, one per device: the
+ * runtime places it when the library's code is loaded on a device and it
+ * stays until the process ends. The call allocates nothing and calls no
+ * allocating routine. Arguments, outputs and results are those of
+ * lpsift_match with the same mp (its kernels run unchanged on the array).
+ * Limit: lpsift_match_workspace_size(nA, nB, n_pairs, mp) must not exceed
+ * LPSIFT_NOALLOC_SCRATCH_BYTES (for one pair of 43,396 x 43,396 descriptors
+ * precision 0 needs ~4 MiB, 1 ~26 MiB, 2 ~15 MiB; 3 fits up to ~25,000).
+ * The array is the one of the current device, so `stream` must belong to
+ * it. Every call on a device shares that device's array and the array keeps
+ * the last call's contents (each call initialises what it reads): calls
+ * that can overlap on one device (different streams, host threads) race and
+ * must be serialised by the caller.
+ * Errors: those of lpsift_match, plus ECAPACITY (workspace need above the
+ * array's size, checked before any GPU work), EINVAL (stream of a device
+ * other than the current one), EUNSUPPORTED (device ordinal >= 64). */
+#define LPSIFT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lpsift_match_noalloc(const float* const* descA, const int64_t* nA,
+                         const float* const* descB, const int64_t* nB, int32_t n_pairs,
+                         const lpsift_match_params* mp, int32_t* const* match, float* const* d1,
+                         float* const* d2, void* stream);
 
 /* The reduced-precision forms of descriptors that lpsift_match contracts at
  * precision 1 and 2 (a precision variant of the Sec. 2.4 contraction; the

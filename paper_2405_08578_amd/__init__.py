@@ -65,7 +65,7 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_match_u8_workspace_size", "lpsift_match_u8",
            "lpsift_describe_multi_workspace_size", "lpsift_describe_multi",
            "lpsift_warp_blend", "lpsift_probe_out_size", "lpsift_probe_ops", "lpsift_probe",
-           "lpsift_quantize_lowp")
+           "lpsift_quantize_lowp", "lpsift_match_noalloc")
 
 _lib = None
 
@@ -105,6 +105,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_match.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
                                  P(lpsift_match_params), c_vp, ctypes.c_size_t, P(c_vp), P(c_vp),
                                  P(c_vp), c_vp]
+    lib.lpsift_match_noalloc.restype = ctypes.c_int
+    lib.lpsift_match_noalloc.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
+                                         P(lpsift_match_params), P(c_vp), P(c_vp), P(c_vp), c_vp]
     lib.lpsift_match_tune.restype = ctypes.c_int
     lib.lpsift_match_tune.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
                                       P(lpsift_match_params), P(c_i32), c_i32, c_i32, c_vp,
@@ -321,6 +324,9 @@ def match_params(ratio: float = 0.8, abs_thresh: float = math.inf, precision: in
     return mp
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20     # LPSIFT_NOALLOC_SCRATCH_BYTES
+
+
 def match_workspace_size(nA: Sequence[int], nB: Sequence[int], mp: lpsift_match_params) -> int:
     n = len(nA)
     return int(load().lpsift_match_workspace_size((c_i64 * n)(*nA), (c_i64 * n)(*nB), n,
@@ -366,6 +372,20 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
     out, head, tail = _match_args(descA, descB, out, workspace,
                                   lambda nA, nB: match_workspace_size(nA, nB, mp), stream)
     _check("lpsift_match", lib.lpsift_match(*head, ctypes.byref(mp), *tail, _stream(stream)))
+    return out
+
+
+def match_noalloc(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
+                  precision: int = 0, b_chunks: int = 0, out=None, stream=None,
+                  stats=None) -> List[Dict[str, "object"]]:
+    """match() through lpsift_match_noalloc: the library's fixed per-device
+    scratch array is the workspace, so with `out` given nothing is allocated.
+    Calls that overlap on one device race on that array."""
+    lib = load()
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
+    out, head, tail = _match_args(descA, descB, out, None, None, stream)
+    _check("lpsift_match_noalloc",
+           lib.lpsift_match_noalloc(*head, ctypes.byref(mp), *tail[2:], _stream(stream)))
     return out
 
 

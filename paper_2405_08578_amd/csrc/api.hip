@@ -3,6 +3,7 @@
 // memory, synchronises, throws or aborts.
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -367,8 +368,8 @@ size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t
 // Everything lpsift_match checks except the workspace size.
 static int check_match_call(const float* const* descA, const int64_t* nA,
                             const float* const* descB, const int64_t* nB, int32_t n_pairs,
-                            const lpsift_match_params* mp, const void* workspace,
-                            int32_t* const* match, float* const* d1, float* const* d2)
+                            const lpsift_match_params* mp, int32_t* const* match,
+                            float* const* d1, float* const* d2)
 {
     const int sp = check_match_params(mp);
     if (sp != LPSIFT_OK) return sp;
@@ -381,7 +382,54 @@ static int check_match_call(const float* const* descA, const int64_t* nA,
         if ((reinterpret_cast<uintptr_t>(descA[i]) | reinterpret_cast<uintptr_t>(descB[i])) & 15u)
             return LPSIFT_EINVAL;
     }
-    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
+    return LPSIFT_OK;
+}
+
+// Splits a validated call's workspace into per-pair slices and launches.
+static int launch_match_call(const float* const* descA, const int64_t* nA,
+                             const float* const* descB, const int64_t* nB, int32_t n_pairs,
+                             const lpsift_match_params* mp, char* ws, int32_t* const* match,
+                             float* const* d1, float* const* d2, hipStream_t stream)
+{
+    std::vector<MatchPairIO> io(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+        io[i] = MatchPairIO{descA[i], nA[i], descB[i], nB[i], ws, match[i], d1[i], d2[i]};
+        ws += align_up(match_workspace_bytes(nA[i], nB[i], mp), 256);
+    }
+    return launch_match_pairs(io.data(), n_pairs, mp, stream);
+}
+
+// The fixed device scratch of lpsift_match_noalloc. Each device holds its own
+// copy (placed when this code object is loaded there) until the process
+// ends. In host code `scratch` names a host-side stand-in, never device
+// memory: the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[LPSIFT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the scratch array on the current device, looked up on the
+// first call made with that device current.
+static int scratch_address(hipStream_t stream, char** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LPSIFT_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return LPSIFT_EUNSUPPORTED;
+    if (stream) {      // the array used is the current device's: the stream must be on it
+        hipDevice_t sd = -1;
+        if (hipStreamGetDevice(stream, &sd) != hipSuccess) return LPSIFT_EHIP;
+        if (sd != dev) return LPSIFT_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LPSIFT_EHIP;
+        g_scratch_dev[dev] = p;
+    }
+    *out = static_cast<char*>(g_scratch_dev[dev]);
     return LPSIFT_OK;
 }
 
@@ -392,16 +440,29 @@ int lpsift_match(const float* const* descA, const int64_t* nA, const float* cons
                  void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                  float* const* d2, void* stream)
 {
-    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, workspace, match, d1, d2);
+    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, match, d1, d2);
     if (sc != LPSIFT_OK) return sc;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
     if (ws_bytes < lpsift_match_workspace_size(nA, nB, n_pairs, mp)) return LPSIFT_ECAPACITY;
-    std::vector<MatchPairIO> io(n_pairs);
-    char* ws = static_cast<char*>(workspace);
-    for (int i = 0; i < n_pairs; ++i) {
-        io[i] = MatchPairIO{descA[i], nA[i], descB[i], nB[i], ws, match[i], d1[i], d2[i]};
-        ws += align_up(match_workspace_bytes(nA[i], nB[i], mp), 256);
-    }
-    return launch_match_pairs(io.data(), n_pairs, mp, static_cast<hipStream_t>(stream));
+    return launch_match_call(descA, nA, descB, nB, n_pairs, mp, static_cast<char*>(workspace),
+                             match, d1, d2, static_cast<hipStream_t>(stream));
+}
+
+int lpsift_match_noalloc(const float* const* descA, const int64_t* nA, const float* const* descB,
+                         const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
+                         int32_t* const* match, float* const* d1, float* const* d2, void* stream)
+{
+    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, match, d1, d2);
+    if (sc != LPSIFT_OK) return sc;
+    if (lpsift_match_workspace_size(nA, nB, n_pairs, mp) > (size_t)LPSIFT_NOALLOC_SCRATCH_BYTES)
+        return LPSIFT_ECAPACITY;
+    char* ws = nullptr;
+    const int sa = scratch_address(static_cast<hipStream_t>(stream), &ws);
+    if (sa != LPSIFT_OK) return sa;
+    // every kernel of the call initialises the workspace words it reads
+    // (counters by a fill kernel), so the previous call's contents do not matter
+    return launch_match_call(descA, nA, descB, nB, n_pairs, mp, ws, match, d1, d2,
+                             static_cast<hipStream_t>(stream));
 }
 
 int lpsift_quantize_lowp(const float* desc, int64_t n, int32_t precision, void* q, float* scale,
@@ -619,8 +680,9 @@ int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float*
                       void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
                       float* const* d2, float* ms, int32_t* best, void* stream)
 {
-    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, workspace, match, d1, d2);
+    const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, match, d1, d2);
     if (sc != LPSIFT_OK) return sc;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
     if (!candidates || n_candidates < 1 || reps < 1 || reps > 1000 || !ms || !best)
         return LPSIFT_EINVAL;
     lpsift_match_params m = *mp;

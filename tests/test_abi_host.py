@@ -159,6 +159,30 @@ def test_match_validation_and_workspace(lib):
     assert lp.match_workspace_size([10], [0], mp) >= 0
 
 
+def test_match_noalloc_validation(lib):
+    """The fixed scratch size in the binding equals the header's, and calls
+    whose workspace need exceeds it are rejected before any GPU work."""
+    txt = open(os.path.join(ROOT, "include", "lpsift.h")).read()
+    m = re.search(r"#define LPSIFT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == lp.NOALLOC_SCRATCH_BYTES
+    arr = lambda *v: (ctypes.c_void_p * len(v))(*v)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+
+    def call(mp_, n=43396, dA=FAKE):
+        return lib.lpsift_match_noalloc(arr(dA), i64(n), arr(FAKE), i64(n), 1, ctypes.byref(mp_),
+                                        arr(FAKE), arr(FAKE), arr(FAKE), None)
+    m3 = lp.match_params(precision=3)
+    assert lp.match_workspace_size([43396], [43396], m3) > lp.NOALLOC_SCRATCH_BYTES
+    assert call(m3) == lp.LPSIFT_ECAPACITY
+    for prec in (0, 1, 2):      # these fit at 43,396 x 43,396
+        assert lp.match_workspace_size([43396], [43396], lp.match_params(precision=prec)) \
+            <= lp.NOALLOC_SCRATCH_BYTES
+    assert call(lp.match_params(), n=-1) == lp.LPSIFT_EINVAL
+    assert call(lp.match_params(), dA=FAKE + 4) == lp.LPSIFT_EINVAL
+    assert call(lp.match_params(ratio=0.0)) == lp.LPSIFT_EINVAL
+    assert call(lp.match_params(precision=4)) == lp.LPSIFT_EINVAL
+
+
 def test_match_tune_validation(lib):
     mp = lp.match_params()
     nA, nB = [5000, 300], [4000, 0]
