@@ -39,15 +39,24 @@ def _host(kp) -> Dict[str, np.ndarray]:
     return {k: v.cpu().numpy() for k, v in kp.items()}
 
 
+def hypothesis_samples(n_points: int, n_iter: int, seed: int) -> np.ndarray:
+    """RANSAC's random draws for a pair with n_points matches: n_iter rows of
+    4 distinct match indices, one row per hypothesis, from a seeded PCG64
+    stream (numpy's Generator.choice without replacement)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_iter, 4), dtype=np.int32)
+    for i in range(n_iter):
+        out[i] = rng.choice(n_points, 4, replace=False)
+    return out
+
+
 def ransac_pair(xyA: np.ndarray, xyB: np.ndarray, seed: int, n_iter: int = RANSAC_ITERS,
                 thresh: float = RANSAC_THRESH):
     """Host RANSAC with seeded hypothesis draws; (H or None, inlier mask)."""
-    import synth
     n = len(xyA)
     if n < 4:
         return None, np.zeros(n, bool)
-    samples = synth.ransac_samples(n, n_iter, np.random.default_rng(seed))
-    H, mask, _ = ransac(xyA, xyB, samples, thresh)
+    H, mask, _ = ransac(xyA, xyB, hypothesis_samples(n, n_iter, seed), thresh)
     return H, mask
 
 
@@ -222,6 +231,24 @@ def finish(res, seed: int, H_true: Optional[np.ndarray] = None):
     return out
 
 
+def needs_fallback(res, min_inliers: int = 12) -> bool:
+    """A learned-path pair is redone on the plain path when its RANSAC keeps
+    fewer than min_inliers inliers."""
+    return res["inliers"] < min_inliers
+
+
+def inlier_retention(plain, learned):
+    """(kept, total): of the plain path's RANSAC inliers, as (slot in A, slot
+    in B) pairs, how many are also inliers of the learned path."""
+    pa, pb = plain["inlier_slots"]
+    la, lb = learned["inlier_slots"]
+    if len(pa) == 0:
+        return 0, 0
+    P = pa.astype(np.int64) << 32 | pb.astype(np.int64)
+    Lk = la.astype(np.int64) << 32 | lb.astype(np.int64)
+    return int(np.isin(P, Lk).sum()), int(len(P))
+
+
 def run_pair(imgs, P: Params, weights=None, seed: int = 0, min_inliers: int = 12,
              precision: int = 0, H_true: Optional[np.ndarray] = None):
     """One pair end to end: the learned path with plain fallback when weights
@@ -232,7 +259,7 @@ def run_pair(imgs, P: Params, weights=None, seed: int = 0, min_inliers: int = 12
         return out
     out = finish(learned_gpu(imgs, P, weights, precision=precision), seed, H_true)
     out["path"] = "learned"
-    if out["inliers"] < min_inliers:
+    if needs_fallback(out, min_inliers):
         out = finish(plain_gpu(imgs, P, precision), seed, H_true)
         out["path"] = "fallback"
     return out

@@ -1,12 +1,16 @@
-"""Host-side pieces of bench.py: the one-GPU guard, the kernel table and the
-traffic figure read from the committed counter summary."""
+"""Host-side pieces of bench.py: the one-GPU guard, the kernel table, the
+traffic figure read from the committed counter summary, the support-visit
+count and the tile-pair geometry."""
 import hashlib
+import math
 import os
 import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
 
 import bench  # noqa: E402
 
@@ -28,27 +32,31 @@ def test_kernel_table_means():
 def test_traffic_follows_the_kernel_source_hash():
     sha = hashlib.sha256(open(bench.MATCH_SRC, "rb").read()).hexdigest()
     recorded = None
-    for line in open(bench.TRAFFIC_FILE):
-        if line.strip().startswith("- match.hip sha256:"):
-            recorded = line.split(":", 1)[1].strip()
+    if os.path.exists(bench.TRAFFIC_FILE):
+        for line in open(bench.TRAFFIC_FILE):
+            if line.strip().startswith("- match.hip sha256:"):
+                recorded = line.split(":", 1)[1].strip()
     t = bench.measured_traffic()
     if recorded == sha:
-        assert t is not None and t > 48777104          # above the algorithmic bytes
+        assert t is not None and t > 1e8          # above any launch's algorithmic bytes
     else:
         assert t is None
 
 
-def test_describe_valu_count_follows_the_kernel_source_hash():
-    sha = hashlib.sha256(open(bench.DESC_SRC, "rb").read()).hexdigest()
-    recorded = None
-    for line in open(bench.DESC_COUNTERS_FILE):
-        if line.strip().startswith("- describe.hip sha256:"):
-            recorded = line.split(":", 1)[1].strip()
-    n = bench.describe_valu_instructions()
-    if recorded == sha:
-        assert n is not None and n > 1e6
-    else:
-        assert n is None
+def test_support_visits_and_sides():
+    ws = bench.subregion_sides([16, 32, 64, 128])
+    assert np.allclose(ws, [4.0, math.sqrt(32), 8.0, math.sqrt(128)], rtol=1e-14)
+    v = bench.support_visits([16], [4.0])
+    # square of side 20 (400) + the 113 integer points of the radius-6 disc
+    assert v == [400.0 + 113]
+
+
+def test_pair_geometry_of_the_grid():
+    class T:
+        order = np.arange(9)
+    nb, far = bench.pair_geometry(T)
+    assert len(nb) == 12 and len(far) == 16       # 8 diagonal pairs are neither
+    assert (0, 1) in nb and (0, 3) in nb and (0, 2) in far and (0, 4) not in far + nb
 
 
 def test_committed_figure_reads_key_lines(tmp_path):

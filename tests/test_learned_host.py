@@ -42,3 +42,22 @@ def test_gt_consistent_count():
     b[2] += [3.5, 0]                                 # 3.5 px off
     assert L.gt_consistent(a, b, H) == 2
     assert L.gt_consistent(a[:0], b[:0], H) == 0
+
+
+def test_hypothesis_samples_are_the_generator_draws():
+    """The package's RANSAC draws are the seeded input generator's draws (the
+    stream the host and oracle RANSAC tests use)."""
+    import synth
+    for n, it, seed in ((4, 10, 0), (57, 300, 5), (1000, 50, 11)):
+        a = L.hypothesis_samples(n, it, seed)
+        b = synth.ransac_samples(n, it, np.random.default_rng(seed))
+        assert np.array_equal(a, b)
+        assert np.all(np.sort(a, axis=1)[:, 1:] != np.sort(a, axis=1)[:, :-1])
+
+
+def test_inlier_retention_counts_slot_pairs():
+    pl = {"inlier_slots": (np.array([1, 2, 3, 7]), np.array([10, 20, 30, 70]))}
+    le = {"inlier_slots": (np.array([2, 3, 7, 9]), np.array([20, 31, 70, 90]))}
+    assert L.inlier_retention(pl, le) == (2, 4)        # (2, 20) and (7, 70)
+    assert L.inlier_retention({"inlier_slots": (np.array([], int), np.array([], int))}, le) == (0, 0)
+    assert L.needs_fallback({"inliers": 11}) and not L.needs_fallback({"inliers": 12})
