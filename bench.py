@@ -74,8 +74,9 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=2,
                     help="runs of the oracle on the sampled pair on all threads")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="before warm-up, copy a buffer of this size once (untimed): a plain "
-                         "copy kernel of known traffic for calibrating HBM counters")
+                    help="before the timed region, add 1 to a buffer of this size once "
+                         "(untimed): an elementwise kernel of known traffic for calibrating "
+                         "HBM counters")
     return ap.parse_args()
 
 
@@ -213,7 +214,7 @@ def headline(args, dev, tiles, flush, out):
     torch.cuda.synchronize()
     A = [ap.desc[i] for i, _ in ap.pairs]
     B = [ap.desc[j] for _, j in ap.pairs]
-    tunes = {prec: lp.match_tune(A, B, precision=prec, candidates=(1, 2, 3, 4, 6, 8), reps=1)
+    tunes = {prec: lp.match_tune(A, B, precision=prec, candidates=(2, 4, 6, 8, 12, 16), reps=1)
              for prec in (0, 3)}
     log("tuned:", {p: t["b_chunks"] for p, t in tunes.items()})
     del A, B, ap
@@ -227,10 +228,12 @@ def headline(args, dev, tiles, flush, out):
     torch.cuda.synchronize()
 
     if args.copy_probe_mb > 0:
+        # an elementwise kernel that reads and writes exactly this many bytes
+        # (a plain copy_ would go to the DMA engines, not a kernel)
         nb = args.copy_probe_mb << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
@@ -344,8 +347,8 @@ def headline(args, dev, tiles, flush, out):
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4),
                      "traffic": measured_traffic(),
-                     "kernel": f"match_topk_f32_kernel: {launches:g} launches per step "
-                               f"(16, 16 and 4 pairs), {flops / 1e12:.3f} TFLOP per step = "
+                     "kernel": f"match_topk_f32_kernel: {launches:g} launch(es) per step "
+                               f"(up to 36 pairs per launch), {flops / 1e12:.3f} TFLOP per step = "
                                f"{flops_per_launch / 1e9:.1f} GFLOP per launch on average, "
                                f"{mk['ms_per_launch']:.4f} ms per launch (HIP events on its "
                                f"stream, instrumented pass)"},

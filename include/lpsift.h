@@ -127,7 +127,8 @@ typedef struct lpsift_keypoints {
  *              0 = FP32 matrix cores; exact up to FP32 rounding.
  *              1 = BF16 inputs, FP32 accumulation; the 8 best kept candidates
  *                  per query are rescored: approximate (a true nearest
- *                  neighbour can be missed).
+ *                  neighbour can be missed; ties are resolved to the lowest
+ *                  index among the rescored candidates).
  *              2 = FP8 E4M3 inputs with one scale per descriptor, FP32
  *                  accumulation, 8 candidates rescored: approximate.
  *              3 = FP32 split into two BF16 parts (three BF16 products per
@@ -304,7 +305,7 @@ size_t lpsift_match_workspace_size(const int64_t* nA, const int64_t* nB, int32_t
  *  descA, descB  host arrays of n_pairs device pointers to float[n][128]
  *  nA, nB        host arrays of n_pairs counts (nA >= 0, nB >= 0)
  *  match, d1, d2 host arrays of n_pairs device pointers to int32/float[nA]
- * Precisions 0 and 3 run up to 16 pairs per kernel launch, and the norms of a
+ * Precisions 0 and 3 run up to 36 pairs per kernel launch, and the norms of a
  * registered set that several pairs share (same pointer and count) are
  * computed once per call: all-pairs matching of N images costs a handful of
  * launches. Outputs must not overlap any input or each other.

@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     }
     if (!live) slot = 0;
     const DescImg& I = a.img[im];
-    const ScaleGeom& G = a.geom[sc];
+    const ScaleGeom G = a.geom[sc];   // a copy: its fields stay in registers through the visit loops
     const int kx = I.x[slot], ky = I.y[slot];
     const float2* field = I.field;
     const int W = I.w, H = I.h;
@@ -639,7 +639,7 @@ void orient_describe_half_kernel(DescArgs a, const int32_t* tables)
     }
     if (!live) slot = 0;
     const DescImg& I = a.img[im];
-    const ScaleGeom& G = a.geom[sc];
+    const ScaleGeom G = a.geom[sc];   // a copy: its fields stay in registers through the visit loops
     const int kx = I.x[slot], ky = I.y[slot];
     const float2* field = I.field;
     const int W = I.w, H = I.h;

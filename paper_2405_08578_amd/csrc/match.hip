@@ -376,7 +376,7 @@ __device__ inline float group_sqdist(const float (&a)[8], const float* __restric
 }
 
 __device__ inline void rescore_f32_query(const float* __restrict__ A, const float* __restrict__ B,
-                                         int chunks, int64_t i, int64_t q,
+                                         int64_t nB, int chunks, int64_t i, int64_t q,
                                          const int32_t* __restrict__ cidx,
                                          const float* __restrict__ cscore, double ratio,
                                          float abs_thresh, int32_t* __restrict__ match,
@@ -426,6 +426,21 @@ __device__ inline void rescore_f32_query(const float* __restrict__ A, const floa
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (k < cnt) best2_insert(group_sqdist(a, B + (int64_t)pick[k] * 128, t), pick[k], e1, j1, e2, j2);
+    }
+    // Without a ratio test an exact tie d1 = d2 is kept, and the nearest
+    // neighbour must then be the lowest tied index. The contraction's lane
+    // top-2 keeps the lowest accumulator rows of a tie, not the lowest
+    // indices, so with three or more tied candidates a lower one may be
+    // missing: search the indices below j1 directly (e1, j1 are equal in
+    // the 16 lanes of the group, so the loop is uniform there).
+    if (__builtin_isinf(ratio) && j1 > 0 && e1 == e2 && sqrtf(e1) < abs_thresh) {
+        const int64_t lim = j1 < nB ? (int64_t)j1 : nB;
+        for (int64_t j = 0; j < lim; ++j) {
+            if (group_sqdist(a, B + j * 128, t) == e1) {
+                j1 = (int)j;
+                break;
+            }
+        }
     }
     if (t == 0) write_result(q, e1, j1, e2, ratio, abs_thresh, match, d1out, d2out);
 }
@@ -501,6 +516,9 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* __restrict__
 #pragma unroll
         for (int k = 0; k < 8; ++k) m = fmaxf(m, fabsf(v[k]));
         for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 16));
+        // scale m / 448: the row maximum maps to 448 exactly, and with it the
+        // many entries that the descriptor's clipping made equal to it (a
+        // power-of-two scale would round them, measured to cost recall)
         const float s = (m > 0.0f) ? m / kFp8Max : 1.0f;
         const float inv = (m > 0.0f) ? kFp8Max / m : 1.0f;
         float x[8];
@@ -520,8 +538,10 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float* __restrict__
 
 // Contraction + per-lane top-K of packed keys for one (query block, chunk).
 // keys[((i * chunks + chunk) * 2 + h) * K + {0 .. K-1}] = lane half h's best K
-// keys of query i, ascending (0xFFFFFFFF = none). key = (float bits of score & ~idx_mask) | index
-// in chunk, score = |b|^2 + C - 2 a.b > 0 (C from the per-call scalars).
+// keys of query i, ascending (0xFFFFFFFF = none). key = (float bits of
+// -score / 2 & ~idx_mask) | index in chunk, score = |b|^2 + C - 2 a.b > 0 (C
+// from the per-call scalars): negative floats, whose bits ascend with their
+// magnitude.
 // Two workgroups per CU: within the 256 registers a lane then has, the
 // accumulators are ordinary VGPRs that the epilogue reads directly (with
 // more registers the compiler places them in AGPRs, and every score costs
@@ -538,8 +558,9 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
     constexpr int kLRow = T::kRowBytes + 16;   // padded LDS row
     constexpr int kU4 = kLpCT * T::kRowBytes / 16 / 256;   // uint4 per thread per tile
     __shared__ __attribute__((aligned(16))) uint8_t tile[kLpCT * kLRow];
-    __shared__ float tnb[kLpCT];
-    __shared__ float tsb[kLpCT];
+    // -(|b|^2 + C) / 2 per tile row: the accumulators' starting values
+    __shared__ __attribute__((aligned(16))) float tnb[kLpCT];
+    __shared__ float tsb[kLpCT];                // candidate scales (FP8)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -551,7 +572,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
     // queries: set t, operand step s -> bytes [(s*KStep + h*KStep/2)*esize, +OpBytes)
     constexpr int kQRegs = T::kOpBytes / 16;   // uint4 per operand
     uint4 qv[kLpSets][T::kSteps][kQRegs];
-    float qs2[kLpSets];                         // -2 x query scale (FP8)
+    float qs[kLpSets];                          // query scale (FP8)
     int64_t qi[kLpSets];
 #pragma unroll
     for (int t = 0; t < kLpSets; ++t) {
@@ -565,7 +586,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
                 qv[t][s][u] = (q < nA) ? *reinterpret_cast<const uint4*>(
                                              row + (s * T::kKStep + h * T::kKStep / 2) * T::kEsize + 16 * u)
                                        : make_uint4(0u, 0u, 0u, 0u);
-        qs2[t] = (P == 2) ? -2.0f * ((q < nA) ? sA[q] : 0.0f) : -2.0f;
+        qs[t] = (P == 2 && q < nA) ? sA[q] : 0.0f;
     }
     uint32_t k1[kLpSets], k2[kLpSets], k3[kLpSets];
 #pragma unroll
@@ -598,7 +619,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
         }
         if (tid < kLpCT) {
             const int64_t j = t0 + tid;
-            tnb[tid] = (j < ce) ? nrmB[j] + C : INFINITY;
+            tnb[tid] = (j < ce) ? -0.5f * (nrmB[j] + C) : -INFINITY;
             tsb[tid] = (P == 2 && j < ce) ? sB[j] : 1.0f;
         }
         __syncthreads();
@@ -607,11 +628,23 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
 
 #pragma unroll 1
         for (int sub = 0; sub < kLpCT / 32; ++sub) {
+            // BF16: every accumulator starts at -(|b|^2 + C) / 2 of its row
+            // (the same for all four query sets: the first MFMA of each set
+            // takes these registers as its addend), so that it ends at
+            // a.b - (|b|^2 + C) / 2 = -score / 2 < 0 without an epilogue FMA.
+            // FP8 accumulates the codes from zero; its row scales are applied
+            // in the epilogue. Rows of the lane: 8 i + 4 h + 0..3 of the half.
+            floatx16 init;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 v = (P == 1) ? *reinterpret_cast<const float4*>(&tnb[sub * 32 + 8 * i + 4 * h])
+                                          : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                init[4 * i] = v.x;
+                init[4 * i + 1] = v.y;
+                init[4 * i + 2] = v.z;
+                init[4 * i + 3] = v.w;
+            }
             floatx16 acc[kLpSets];
-#pragma unroll
-            for (int t = 0; t < kLpSets; ++t)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
             const uint8_t* trow = &tile[(sub * 32 + col) * kLRow];
 #pragma unroll
             for (int s = 0; s < T::kSteps; ++s) {
@@ -622,10 +655,11 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
                         trow + (s * T::kKStep + h * T::kKStep / 2) * T::kEsize + 16 * u);
 #pragma unroll
                 for (int t = 0; t < kLpSets; ++t) {
+                    const floatx16 addend = (s == 0) ? init : acc[t];
                     if constexpr (P == 1) {
                         acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             __builtin_bit_cast(bf16x8, av[0]), __builtin_bit_cast(bf16x8, qv[t][s][0]),
-                            acc[t], 0, 0, 0);
+                            addend, 0, 0, 0);
                     } else {
                         const intx8 a8 = {(int)av[0].x, (int)av[0].y, (int)av[0].z, (int)av[0].w,
                                           (int)av[1].x, (int)av[1].y, (int)av[1].z, (int)av[1].w};
@@ -633,17 +667,19 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
                                           (int)qv[t][s][0].w, (int)qv[t][s][1].x, (int)qv[t][s][1].y,
                                           (int)qv[t][s][1].z, (int)qv[t][s][1].w};
                         acc[t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            a8, b8, acc[t], 0, 0, 0, 0, 0, 0);
+                            a8, b8, addend, 0, 0, 0, 0, 0, 0);
                     }
                 }
             }
-            // epilogue: key = (score bits & ~mask) | index in chunk, top-K by
-            // min / med3 (keys are unique)
+            // epilogue: key = (accumulator bits & ~mask) | index in chunk.
+            // The accumulators are negative, so their bits (sign set) order
+            // like their magnitudes, i.e. like the scores; top-K by min /
+            // med3 (keys are unique)
             auto lp_key = [&](int t, int r) {
                 const int cl = sub * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const float sc = (P == 1) ? fmaf(-2.0f, acc[t][r], tnb[cl])
-                                          : fmaf(qs2[t] * tsb[cl], acc[t][r], tnb[cl]);
-                return (__float_as_uint(sc) & ~idx_mask) | (local0 + (uint32_t)cl);
+                // FP8: -score / 2 = sA sB qa.qb - (|b|^2 + C) / 2
+                const float v = (P == 1) ? acc[t][r] : fmaf(qs[t] * tsb[cl], acc[t][r], tnb[cl]);
+                return (__float_as_uint(v) & ~idx_mask) | (local0 + (uint32_t)cl);
             };
             if constexpr (K == 2) {
                 // two rows at a time: for k1 <= k2 and new keys x, y the two
@@ -706,9 +742,11 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
         sc[u] = INFINITY;
         jv[u] = -1;
         if (e < ne) {
+            // keys are the bits of negative accumulators (sign set, below
+            // -inf's 0xFF800000): their magnitudes are half the scores
             const uint32_t key = keys[q * ne + e];
-            if (key < 0x7F800000u) {
-                sc[u] = __uint_as_float(key & ~idx_mask);
+            if (key >= 0x80000000u && key < 0xFF800000u) {
+                sc[u] = __uint_as_float(key & ~idx_mask & 0x7FFFFFFFu);
                 jv[u] = (int64_t)(e / (2 * K)) * chunk_len + (key & idx_mask);
             }
         }
@@ -1101,7 +1139,9 @@ __global__ void lp_scalars_kernel(float* scal, float dot_err)
 // they are evaluated inside the kernel; such launches use a grid smaller than
 // the largest possible item range and stride over it.
 
-constexpr int kPairs = 16;
+// 36 pairs: all pairs of 9 images in one launch. The largest job table
+// (RescoreX3Batch, 104 B per job) then stays below 4 KB of kernel arguments.
+constexpr int kPairs = 36;
 
 // Job k of batch b that item `it` belongs to (-1 past the end) and the item's
 // index within that job. items(job) must be uniform across the workgroup.
@@ -1233,6 +1273,7 @@ struct RescoreF32Job {
     float* d1;
     float* d2;
     int64_t nq;
+    int64_t nB;
     int32_t chunks;
 };
 struct RescoreF32Batch {
@@ -1255,7 +1296,7 @@ __global__ __launch_bounds__(256) void rescore_f32_kernel(const RescoreF32Batch 
         const int64_t nq = J.qlist ? (int64_t)*J.qcount : J.nq;
         const int64_t i = local * 16 + (threadIdx.x >> 4);   // 16 queries per workgroup
         if (i < nq)
-            rescore_f32_query(J.A, J.B, J.chunks, i, J.qlist ? J.qlist[i] : i, J.cidx, J.cscore,
+            rescore_f32_query(J.A, J.B, J.nB, J.chunks, i, J.qlist ? J.qlist[i] : i, J.cidx, J.cscore,
                               b.ratio, b.abs_thresh, J.match, J.d1, J.d2);
     }
 }
@@ -1333,7 +1374,12 @@ struct CounterBatch {
     int32_t n;
     uint32_t* c[kPairs];
 };
+static_assert(sizeof(RowsBatch) <= 4096 && sizeof(F32Batch) <= 4096 && sizeof(X3Batch) <= 4096 &&
+                  sizeof(RescoreF32Batch) <= 4096 && sizeof(RescoreX3Batch) <= 4096,
+              "job tables are kernel arguments: keep them within 4 KB");
 
+// Four counter words per job; launched with kCounterThreads >= 4 kPairs threads.
+constexpr int kCounterThreads = 4 * kPairs;
 __global__ void zero_counters_kernel(const CounterBatch b, int words)
 {
     const int k = threadIdx.x / 4, w = threadIdx.x % 4;
@@ -1661,7 +1707,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
             const PairPtrs& Q = pp[i];
             if (P.nB == 0) {            // no candidates: every query rejected
                 rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, nullptr, nullptr,
-                                             P.match, P.d1, P.d2, P.nA, 0};
+                                             P.match, P.d1, P.d2, P.nA, P.nB, 0};
                 rf_most += (P.nA + 15) / 16;
                 continue;
             }
@@ -1681,7 +1727,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
                                           P.nA, P.nB, Q.pf.chunk_len, Q.pf.chunks};
                 main_wg += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
                 rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, Q.fidx, Q.fscore,
-                                             P.match, P.d1, P.d2, P.nA, Q.pf.chunks};
+                                             P.match, P.d1, P.d2, P.nA, P.nB, Q.pf.chunks};
                 rf_most += (P.nA + 15) / 16;
                 continue;
             }
@@ -1697,12 +1743,12 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
                                       Q.pf.chunk_len, Q.pf.chunks};
             fall_most += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
             rf.j[rf.n++] = RescoreF32Job{P.A, P.B, Q.fb, Q.cnt, Q.fidx, Q.fscore, P.match, P.d1,
-                                         P.d2, P.nA, Q.pf.chunks};
+                                         P.d2, P.nA, P.nB, Q.pf.chunks};
             rf_most += (P.nA + 15) / 16;
         }
         // the split rows' maxima are accumulated with atomics: zero them first
         if (cnt.n > 0)
-            hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, cnt, 4);
+            hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(kCounterThreads), 0, stream, cnt, 4);
         if (rows.n > 0) {
             TimedScope ts(LPSIFT_KERNEL_MATCH_NORMS, stream);
             hipLaunchKernelGGL(rows_kernel, dim3((unsigned)rows_wg), dim3(256), 0, stream, rows);

@@ -213,6 +213,38 @@ def test_match_config1_sampled_queries(gpu):
     check_rule_i(A32[idx], B32, {k: v[idx] for k, v in g.items()})
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("chunks", [0, 1, 3])
+def test_match_threshold_only_exact_ties_lowest_index(gpu, precision, chunks):
+    """Eq. 6's absolute threshold alone (ratio = +inf) keeps a tied nearest
+    neighbour, so the reported index must be the lowest of the tie. Zero
+    candidates at rows 3, 32, 33, 35, 67 and copies of one row at 8, 40, 72
+    (the same accumulator row of three 32-row tiles and rows of both lane
+    halves) are three-way or larger exact ties for zero queries and for the
+    copied row's own queries; the lane top-2 of the contraction keeps the
+    lowest accumulator rows, not the lowest indices."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    nB = 200
+    B = synth.random_unit_rows(nB, 128, rng).astype(np.float32)
+    zeros = [3, 32, 33, 35, 67]
+    B[zeros] = 0.0
+    src = B[150].copy()
+    copies = [8, 40, 72, 150]
+    B[copies] = src
+    A = synth.noisy_copies(B.astype(np.float64), rng.integers(0, nB, 60), 0.05, rng).astype(np.float32)
+    A[:4] = 0.0
+    A[4:8] = src
+    say("threshold-only exact ties", precision, chunks)
+    g = run_match(gpu, A, B, precision=precision, ratio=math.inf, b_chunks=chunks)
+    o = oracle.match(A.astype(np.float64), B.astype(np.float64), ratio=math.inf)
+    assert np.all(g["match"][:4] == 3) and np.all(o["match"][:4] == 3)
+    assert np.all(g["match"][4:8] == 8) and np.all(o["match"][4:8] == 8)
+    assert np.all(g["d1"][:8] == 0.0) and np.all(g["d2"][:8] == 0.0)
+    safe = match_margins(o["d1"], o["d2"], 0.8) > 1e-6
+    safe[:8] = True
+    assert np.array_equal(g["match"][safe], o["match"][safe])
+
+
 def test_match_deterministic(gpu):
     rng = np.random.Generator(np.random.PCG64(21))
     B = synth.random_unit_rows(3000, 128, rng).astype(np.float32)

@@ -1,6 +1,6 @@
 """Many pairs in one lpsift_match call.
 
-The FP32 and split paths run up to 16 pairs per launch and compute the norms
+The FP32 and split paths run up to 36 pairs per launch and compute the norms
 of a registered set shared by several pairs once; every pair's lists must be
 bit-identical to the same pair matched alone (the per-pair arithmetic does not
 depend on the batch), and the split path's re-match count must be the sum of
@@ -39,7 +39,9 @@ def host(r):
 @pytest.mark.parametrize("prec", [0, 3, 1, 2])
 def test_batch_equals_pairs_alone(gpu, prec):
     import torch
-    sizes = [700, 450, 1000, 37, 0, 260]            # 30 ordered pairs: two batches of 16 and 14
+    # 42 ordered pairs: launches of 36 and 6 pairs (the counters of every job
+    # of a launch are cleared and summed, which the re-match count checks)
+    sizes = [700, 450, 1000, 37, 0, 260, 333]
     sets = [torch.from_numpy(s).to(gpu) for s in descriptor_sets(sizes, 40 + prec)]
     pairs = all_pairs(len(sets))
     say("batched match", prec, len(pairs), "pairs")
