@@ -31,7 +31,11 @@ from . import (DESC_DIM, Params, ScorerTrainer, describe, describe_selected,
                SCORER_PARAMS)
 
 WEIGHTS_VERSION = 1
-RANSAC_ITERS = 2000
+# Hypotheses per host RANSAC. 20,000 keep the best hypothesis stable from
+# run to run on these pairs (inlier ratios down to ~2 %): with 2,000, about
+# 1 % of the inliers of a pair came and went with the draws, which the
+# learned path's retention would otherwise count as lost.
+RANSAC_ITERS = 20000
 RANSAC_THRESH = 3.0
 
 
@@ -40,14 +44,17 @@ def _host(kp) -> Dict[str, np.ndarray]:
 
 
 def hypothesis_samples(n_points: int, n_iter: int, seed: int) -> np.ndarray:
-    """RANSAC's random draws for a pair with n_points matches: n_iter rows of
-    4 distinct match indices, one row per hypothesis, from a seeded PCG64
-    stream (numpy's Generator.choice without replacement)."""
+    """RANSAC's random draws for a pair with n_points >= 4 matches: n_iter
+    rows of 4 distinct match indices, one row per hypothesis, from a seeded
+    PCG64 stream (uniform rows; rows with a repeated index are drawn again)."""
     rng = np.random.default_rng(seed)
-    out = np.empty((n_iter, 4), dtype=np.int32)
-    for i in range(n_iter):
-        out[i] = rng.choice(n_points, 4, replace=False)
-    return out
+    out = rng.integers(0, n_points, size=(n_iter, 4), dtype=np.int64)
+    while True:
+        s = np.sort(out, axis=1)
+        bad = np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
+        if len(bad) == 0:
+            return out.astype(np.int32)
+        out[bad] = rng.integers(0, n_points, size=(len(bad), 4), dtype=np.int64)
 
 
 def ransac_pair(xyA: np.ndarray, xyB: np.ndarray, seed: int, n_iter: int = RANSAC_ITERS,
@@ -295,8 +302,9 @@ def pair_records(imgs, P: Params, seed: int, neg_per_pos: int = 4):
 
 
 def train(patches, extra, labels, init, steps: int, batch: int = 8192, lr: float = 1e-3,
-          seed: int = 0, log=None, lr_final: float = 1.0):
-    """Adam on balanced class weights over shuffled minibatches, the step size
+          seed: int = 0, log=None, lr_final: float = 1.0, pos_weight_scale: float = 1.0):
+    """Adam on class-weighted BCE over shuffled minibatches (positives weighted
+    pos_weight_scale x n_neg / n_pos: 1 balances the classes), the step size
     decaying from lr to lr * lr_final on a half cosine; returns the FP32
     weights (device) and the loss history."""
     import math
@@ -304,7 +312,7 @@ def train(patches, extra, labels, init, steps: int, batch: int = 8192, lr: float
     dev = patches.device
     n = int(labels.numel())
     pos = float(labels.sum().item())
-    w_pos = (n - pos) / max(pos, 1.0)
+    w_pos = pos_weight_scale * (n - pos) / max(pos, 1.0)
     cweight = torch.where(labels > 0.5, torch.tensor(w_pos, device=dev),
                           torch.tensor(1.0, device=dev)).float().contiguous()
     tr = ScorerTrainer(torch.from_numpy(np.asarray(init, np.float32).copy()).to(dev), batch)

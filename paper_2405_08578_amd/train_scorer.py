@@ -9,7 +9,8 @@ Pairs are generated like the 2600x1600 benchmark pair (instances 100 ..
 RANSAC; the inlier endpoints are the positives (see learned.pair_records).
 Training runs lpsift_scorer_train_step with class-balanced weights. A few
 held-out pairs (instances 900 ..) then compare the learned path's RANSAC
-inliers with the plain path's; the result goes into the weight file's
+inliers with the plain path's (the share of the plain inliers, as slot pairs,
+that the learned path keeps); the result goes into the weight file's
 metadata.
 """
 from __future__ import annotations
@@ -83,16 +84,19 @@ def main(argv=None):
                         seed=args.seed, log=log, lr_final=args.lr_final)
     torch.cuda.synchronize()
 
-    # held-out comparison: learned (no fallback) vs plain inliers
+    # held-out comparison: learned (no fallback) vs plain; retention = the
+    # plain path's RANSAC inliers (slot pairs) that the learned path keeps
     ev = []
     evi = list(range(900, 900 + args.eval_pairs))
     for inst, A, B, H in pool.imap(_make, evi, chunksize=1):
         imgs = [torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)]
         pl = L.run_pair(imgs, P, None, seed=inst, H_true=H)
         le = L.run_pair(imgs, P, w, seed=inst, min_inliers=0, H_true=H)
-        ev.append((inst, pl["inliers"], le["inliers"], pl["gt_consistent"], le["gt_consistent"]))
-        log(f"held-out {inst}: RANSAC inliers plain {pl['inliers']} learned {le['inliers']}; "
-            f"ground-truth-consistent matches plain {pl['gt_consistent']} learned "
+        kept, tot = L.inlier_retention(pl, le)
+        ev.append((inst, pl["inliers"], le["inliers"], pl["gt_consistent"], le["gt_consistent"],
+                   kept))
+        log(f"held-out {inst}: RANSAC inliers plain {pl['inliers']} learned {le['inliers']} "
+            f"kept {kept}; ground-truth-consistent matches plain {pl['gt_consistent']} learned "
             f"{le['gt_consistent']}")
     pool.close()
     pool.join()
@@ -100,20 +104,26 @@ def main(argv=None):
     tot_l = sum(e[2] for e in ev)
     gt_p = sum(e[3] for e in ev)
     gt_l = sum(e[4] for e in ev)
+    kept_all = sum(e[5] for e in ev)
     meta = {"train_pairs": args.pairs, "train_instances": [insts[0], insts[-1]],
             "pair_config": "2600x1600 blob-texture pairs, random similarity, IoU 0.3-0.5",
             "L": [16, 32, 64, 128], "records": int(labels.numel()), "positives": n_pos,
             "steps": args.steps, "batch": args.batch, "lr": args.lr,
             "lr_final": args.lr_final, "neg_per_pos": args.neg_per_pos, "seed": args.seed,
             "loss_history": losses,
+            "ransac_iters": L.RANSAC_ITERS,
             "heldout": [dict(zip(("instance", "ransac_plain", "ransac_learned", "gt_plain",
-                                  "gt_learned"), e)) for e in ev],
-            "heldout_inlier_retention": (tot_l / tot_p) if tot_p else None,
+                                  "gt_learned", "plain_inliers_kept"), e)) for e in ev],
+            "heldout_inlier_retention": (kept_all / tot_p) if tot_p else None,
+            "heldout_inlier_retention_min_pair": min(e[5] / max(e[1], 1) for e in ev) if ev else None,
+            "heldout_inlier_count_ratio": (tot_l / tot_p) if tot_p else None,
             "heldout_gt_match_retention": (gt_l / gt_p) if gt_p else None}
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     L.save_weights(args.out, w.cpu().numpy(), meta)
-    log(f"saved {args.out}.bin / .json; held-out retention: RANSAC inliers "
-        f"{meta['heldout_inlier_retention']}, ground-truth-consistent matches "
+    log(f"saved {args.out}.bin / .json; held-out retention of the plain RANSAC inliers "
+        f"{meta['heldout_inlier_retention']} (lowest pair "
+        f"{meta['heldout_inlier_retention_min_pair']}), inlier count ratio "
+        f"{meta['heldout_inlier_count_ratio']}, ground-truth-consistent matches "
         f"{meta['heldout_gt_match_retention']}")
     return 0
 
