@@ -150,3 +150,106 @@ def seam_errors(G, G_true, shapes, step: int = 64) -> Dict[tuple, float]:
             d = np.linalg.norm(a[:, :2] / a[:, 2:] - b[:, :2] / b[:, 2:], axis=1)
             out[(i, j)] = float(d.max())
     return out
+
+
+def _map(G: np.ndarray, p: np.ndarray) -> np.ndarray:
+    q = p @ G[:, :2].T + G[:, 2]
+    return q[:, :2] / q[:, 2:3]
+
+
+def refine(G, correspondences, reference: int, iters: int = 20, lam: float = 1e-3):
+    """Joint refinement of the placed transforms (a step beyond Sec. 4, whose
+    rounds chain pair homographies: errors then add up along the chain, and
+    overlaps between images placed through different links do not agree).
+    Every transform G_k (image k -> reference pixels, h33 = 1) except the
+    reference's is adjusted to minimise the sum over all stitchable pairs
+    (i, j) and their RANSAC-inlier correspondences (p_i, p_j) of
+    |G_i(p_i) - G_j(p_j)|^2 in reference pixels, by Levenberg-Marquardt with
+    the chained transforms as the start; the reference stays the identity.
+    correspondences: list of (i, j, P_i [m, 2], P_j [m, 2]) in pixels.
+    Returns (the refined transform list, {"rms_before", "rms_after", "iters"})."""
+    n = len(G)
+    free = [k for k in range(n) if G[k] is not None and k != reference]
+    pos = {k: t for t, k in enumerate(free)}
+    used = [(i, j, np.asarray(a, np.float64), np.asarray(b, np.float64))
+            for i, j, a, b in correspondences
+            if G[i] is not None and G[j] is not None and len(a) > 0 and (i in pos or j in pos)]
+    if not free or not used:
+        return [None if g is None else np.asarray(g, np.float64) for g in G], \
+            {"rms_before": 0.0, "rms_after": 0.0, "iters": 0}
+    # normalise pixel coordinates per image for a well-conditioned solve:
+    # parameters are the 8 entries of S G_k S_k^-1 (h33 = 1), with S_k the
+    # image's own scaling and S the reference frame's
+    scale = 1.0 / 1000.0
+    S = np.diag([scale, scale, 1.0])
+    Si = np.diag([1.0 / scale, 1.0 / scale, 1.0])
+
+    def to_params(Gs):
+        x = np.empty(8 * len(free))
+        for k in free:
+            M = S @ Gs[k] @ Si
+            M = M / M[2, 2]
+            x[8 * pos[k]:8 * pos[k] + 8] = M.ravel()[:8]
+        return x
+
+    def from_params(x):
+        out = [None if g is None else np.asarray(g, np.float64) for g in G]
+        for k in free:
+            M = np.append(x[8 * pos[k]:8 * pos[k] + 8], 1.0).reshape(3, 3)
+            out[k] = Si @ M @ S
+        return out
+
+    def residuals(x):
+        Gs = from_params(x)
+        r = [(_map(Gs[i], a) - _map(Gs[j], b)).ravel() for i, j, a, b in used]
+        return np.concatenate(r)
+
+    x = to_params(G)
+    r = residuals(x)
+    rms0 = float(np.sqrt(np.mean(r ** 2)))
+    cost = float(r @ r)
+    it = 0
+    for it in range(1, iters + 1):
+        J = np.empty((r.size, x.size))
+        for c in range(x.size):
+            h = 1e-7 * max(1.0, abs(x[c]))
+            xp = x.copy()
+            xp[c] += h
+            J[:, c] = (residuals(xp) - r) / h
+        A = J.T @ J
+        g = J.T @ r
+        while True:
+            step = np.linalg.solve(A + lam * np.diag(np.diag(A) + 1e-12), -g)
+            xn = x + step
+            rn = residuals(xn)
+            cn = float(rn @ rn)
+            if cn < cost:
+                x, r, cost = xn, rn, cn
+                lam = max(lam / 10.0, 1e-12)
+                break
+            lam *= 10.0
+            if lam > 1e12:
+                break
+        if lam > 1e12 or float(np.linalg.norm(step)) < 1e-12 * (1.0 + float(np.linalg.norm(x))):
+            break
+    out = from_params(x)
+    return out, {"rms_before": rms0, "rms_after": float(np.sqrt(np.mean(r ** 2))), "iters": it}
+
+
+def correspondences(pairs, kps, slotA, slotB, inlier, stats, W):
+    """RANSAC-inlier correspondences of the stitchable pairs (W[i, j] > 0) as
+    (i, j, P_i, P_j) pixel arrays, from host copies of the GPU RANSAC outputs:
+    per pair p the first stats[p, 0] entries of slotA[p], slotB[p], inlier[p];
+    kps[k] holds the keypoint x, y arrays of image k."""
+    out = []
+    for p, (i, j) in enumerate(pairs):
+        if W[i, j] <= 0:
+            continue
+        m = int(stats[p, 0])
+        keep = np.asarray(inlier[p][:m]).astype(bool)
+        sa = np.asarray(slotA[p][:m])[keep]
+        sb = np.asarray(slotB[p][:m])[keep]
+        Pi = np.stack([kps[i]["x"][sa], kps[i]["y"][sa]], axis=1).astype(np.float64)
+        Pj = np.stack([kps[j]["x"][sb], kps[j]["y"][sb]], axis=1).astype(np.float64)
+        out.append((i, j, Pi, Pj))
+    return out
