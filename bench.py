@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline step (tuning, cold and warm replays, the "
                          "instrumented pass): for profiler runs")
+    ap.add_argument("--pair-only", action="store_true",
+                    help="only the 2600x1600 pair section, printed as one JSON line: for "
+                         "profiler runs of detect and describe")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-pruning side measurement (32 mixed-size pairs)")
     ap.add_argument("--learned-pairs", type=int, default=32)
@@ -873,6 +876,12 @@ def main():
 
     # mixed-size pairs for the learned-pruning measurement: rendered by host
     # processes started before this process touches the GPU
+    if args.pair_only:
+        import torch
+        dev = torch.device("cuda:0")
+        print(json.dumps({"pair_2600x1600": single_pair(args, dev, Flush(dev))}), flush=True)
+        return
+
     learned_job = pool = None
     if not (args.no_learned or args.headline_only):
         import multiprocessing as mp

@@ -46,6 +46,7 @@ struct TableArgs {
     int32_t n_tables;
     int32_t r2[2 * LPSIFT_MAX_SCALES];
     int32_t off[2 * LPSIFT_MAX_SCALES];
+    float k[2 * LPSIFT_MAX_SCALES];   // Gaussian exponent factor of the table
 };
 
 __device__ inline int32_t pack_offset(int dx, int dy)
@@ -53,11 +54,22 @@ __device__ inline int32_t pack_offset(int dx, int dy)
     return (int32_t)((uint32_t)(dx & 0xFFFF) | ((uint32_t)dy << 16));
 }
 
+// One disc entry: the offset as floats (for the rotation), its Gaussian
+// weight exp2((dx^2 + dy^2) k) (computed once here, with the same product and
+// v_exp_f32 a visit would use), and the packed integer offset (for the field
+// address) -- one 16-byte load per visit.
+__device__ inline float4 disc_entry(int dx, int dy, float k)
+{
+    return make_float4((float)dx, (float)dy,
+                       __builtin_amdgcn_exp2f((float)(dx * dx + dy * dy) * k),
+                       __int_as_float(pack_offset(dx, dy)));
+}
+
 constexpr int kTabThreads = 256;
 
 // One workgroup per table. Thread t owns a contiguous run of rows; a block
 // scan of the per-thread entry counts gives every row its start.
-__global__ __launch_bounds__(kTabThreads) void disc_tables_kernel(TableArgs a, int32_t* tables)
+__global__ __launch_bounds__(kTabThreads) void disc_tables_kernel(TableArgs a, float4* tables)
 {
     __shared__ int scan[kTabThreads];
     const int t = blockIdx.x, tid = threadIdx.x;
@@ -80,11 +92,12 @@ __global__ __launch_bounds__(kTabThreads) void disc_tables_kernel(TableArgs a, i
         __syncthreads();
     }
     int start = scan[tid] - cnt;
-    int32_t* out = tables + a.off[t];
+    float4* out = tables + a.off[t];
+    const float k = a.k[t];
     for (int i = row0; i < row0 + per && i < rows; ++i) {
         const int dy = i - R;
         const int hw = isqrt_floor(r2 - dy * dy);
-        for (int dx = -hw; dx <= hw; ++dx) out[start++] = pack_offset(dx, dy);
+        for (int dx = -hw; dx <= hw; ++dx) out[start++] = disc_entry(dx, dy, k);
     }
 }
 
@@ -266,23 +279,26 @@ __device__ inline float parabola_offset(float hm, float h0, float hp)
 template <int kStride, int kC = kCopies>
 __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bool live, int kx,
                                              int ky, const float2* field, int W, int H,
-                                             const ScaleGeom& G, const int32_t* tables)
+                                             const ScaleGeom& G, const float4* tables)
 {
     const int n = live ? G.n_orient : 0;
     const int per = (n + kStride - 1) / kStride;
-    const int32_t* tab = tables + G.off_orient;
+    const float4* tab = tables + G.off_orient;
     unsigned long long* hv = ho + (sub % kC) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < per; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
         float2 ft[kUnroll];
+        float gw[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int j = (it0 + u) * kStride + sub;
             ok[u] = (it0 + u < per) && j < n;
-            const int32_t e = ok[u] ? tab[j] : 0;
-            dx[u] = (int)(int16_t)(e & 0xFFFF);
-            dy[u] = e >> 16;
+            const float4 e = ok[u] ? tab[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const int32_t pk = __float_as_int(e.w);
+            dx[u] = (int)(int16_t)(pk & 0xFFFF);
+            dy[u] = pk >> 16;
+            gw[u] = e.z;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -293,10 +309,9 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ft[u].x == 0.0f) continue;
-            // the exponent is above -7 for every geometry, far from the
-            // denormal range that exp2f guards against: v_exp_f32 alone
-            const float wt = ft[u].x * kVoteScale *
-                             __builtin_amdgcn_exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_orient);
+            // Gaussian weight from the table (its exponent is above -7 for
+            // every geometry, far from the denormal range: v_exp_f32 alone)
+            const float wt = ft[u].x * kVoteScale * gw[u];
             const float t = ft[u].y * 36.0f;
             const float k0f = floorf(t);
             const float fr = t - k0f;
@@ -312,7 +327,7 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
 template <int kC>
 __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, bool live, int kx,
                                              int ky, const float2* field, int W, int H,
-                                             const ScaleGeom& G, const int32_t* tables)
+                                             const ScaleGeom& G, const float4* tables)
 {
     orient_votes<64, kC>(ho, lane, live, kx, ky, field, W, H, G, tables);
     wave_sync();
@@ -361,7 +376,7 @@ __device__ inline float peak_turns(float sm, int k, float h0)
 template <int kStride, int kC = kCopies>
 __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bool live, int kx,
                                            int ky, const float2* field, int W, int H,
-                                           const ScaleGeom& G, const int32_t* tables,
+                                           const ScaleGeom& G, const float4* tables,
                                            float th_turns)
 {
     float sn, cs;
@@ -370,19 +385,24 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
     const float ca = cs * G.inv_ws, sa = sn * G.inv_ws;   // rotation by -theta, in cells
     const int nd = live ? G.n_desc : 0;
     const int perd = (nd + kStride - 1) / kStride;
-    const int32_t* tabd = tables + G.off_desc;
+    const float4* tabd = tables + G.off_desc;
     unsigned long long* hv = hist + (sub % kC) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < perd; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
         float2 ft[kUnroll];
+        float fdx[kUnroll], fdy[kUnroll], gw[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int j = (it0 + u) * kStride + sub;
             ok[u] = (it0 + u < perd) && j < nd;
-            const int32_t e = ok[u] ? tabd[j] : 0;
-            dx[u] = (int)(int16_t)(e & 0xFFFF);
-            dy[u] = e >> 16;
+            const float4 e = ok[u] ? tabd[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const int32_t pk = __float_as_int(e.w);
+            dx[u] = (int)(int16_t)(pk & 0xFFFF);
+            dy[u] = pk >> 16;
+            fdx[u] = e.x;
+            fdy[u] = e.y;
+            gw[u] = e.z;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -394,12 +414,10 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
         for (int u = 0; u < kUnroll; ++u) {
             if (ft[u].x == 0.0f) continue;
             // offset rotated by -theta, in subregion units
-            const float fdx = (float)dx[u], fdy = (float)dy[u];
-            const float uu = fmaf(ca, fdx, sa * fdy);
-            const float vv = fmaf(ca, fdy, -(sa * fdx));
+            const float uu = fmaf(ca, fdx[u], sa * fdy[u]);
+            const float vv = fmaf(ca, fdy[u], -(sa * fdx[u]));
             if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
-            const float m = ft[u].x * kVoteScale *
-                            __builtin_amdgcn_exp2f((float)(dx[u] * dx[u] + dy[u] * dy[u]) * G.k_desc);
+            const float m = ft[u].x * kVoteScale * gw[u];
             // direction bins o0 and o0 + 1 (mod 8) of the angle relative to theta
             const float t = __builtin_amdgcn_fractf(ft[u].y - th_turns) * 8.0f;   // [0, 8)
             const int o0 = (int)t;
@@ -432,7 +450,7 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
 template <bool kWaveOnly, int kC>
 __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, bool live, int kx,
                                             int ky, const float2* field, int W, int H,
-                                            const ScaleGeom& G, const int32_t* tables,
+                                            const ScaleGeom& G, const float4* tables,
                                             float th_turns, float& r0, float& r1)
 {
     desc_votes<64, kC>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns);
@@ -454,7 +472,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 }
 
 template <int kMode>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void orient_describe_kernel(DescArgs a, const int32_t* tables)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void orient_describe_kernel(DescArgs a, const float4* tables)
 {
     constexpr int kC = mode_copies<kMode>();
     __shared__ unsigned long long hist_mem[kCellPad + kWaves * kC * kBins];
@@ -601,7 +619,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // Same arithmetic as orient_describe_kernel<kModeFull>, except that the
 // normalisation sums add over 32 lanes in a different order.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void orient_describe_half_kernel(DescArgs a, const int32_t* tables)
+void orient_describe_half_kernel(DescArgs a, const float4* tables)
 {
     __shared__ unsigned long long hist_mem[kCellPad + kWaves * 2 * kHalfCopies * kBins];
     __shared__ float smv[kWaves][2][36];
@@ -656,13 +674,23 @@ void orient_describe_half_kernel(DescArgs a, const int32_t* tables)
         for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kBins + 128 + k];
         return (float)v * kVoteInv;
     };
-    auto smooth = [&](int k) {
-        return smooth5(bin((k + 34) % 36), bin((k + 35) % 36), bin(k), bin((k + 1) % 36),
-                       bin((k + 2) % 36));
+    // each bin converted once: lane sub holds bin sub (ha) and, for sub < 4,
+    // bin 32 + sub (hb); a neighbour bin comes from the lane that holds it
+    const float ha = bin(sub);
+    const float hb = sub < 4 ? bin(32 + sub) : 0.0f;
+    auto at = [&](int b) {           // bin b (0 .. 35) of this half's histogram
+        const float va = __shfl(ha, b & 31, 32);
+        const float vb = __shfl(hb, (b - 32) & 31, 32);
+        return b < 32 ? va : vb;
+    };
+    auto smooth = [&](int k, float h0) {
+        return smooth5(at((k + 34) % 36), at((k + 35) % 36), h0, at((k + 1) % 36),
+                       at((k + 2) % 36));
     };
     // lane sub holds bin sub and, for sub < 4, bin 32 + sub
-    const float s1 = smooth(sub);
-    const float s2 = sub < 4 ? smooth(32 + sub) : -1.0f;
+    const float s1 = smooth(sub, ha);
+    const float s2t = smooth(32 + (sub & 3), hb);   // every lane joins the shuffles
+    const float s2 = sub < 4 ? s2t : -1.0f;
     sv[sub] = s1;
     if (sub < 4) sv[32 + sub] = s2;
     float bv = s1;
@@ -784,7 +812,7 @@ __global__ __launch_bounds__(kScanThreads) void orient_scan_kernel(ScanArgs a)
 
 size_t field_offset(const Geometry& g)
 {
-    return align_up((size_t)g.table_entries * 4, 256);
+    return align_up((size_t)g.table_entries * sizeof(float4), 256);
 }
 
 }  // namespace
@@ -820,15 +848,17 @@ int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, c
                  const int64_t* n_sel, const MultiSpec* ms, hipStream_t stream)
 {
     char* base = static_cast<char*>(ws);
-    int32_t* tables = reinterpret_cast<int32_t*>(base);
+    float4* tables = reinterpret_cast<float4*>(base);
 
     TableArgs ta{};
     ta.n_tables = 2 * g.n_scales;
     for (int s = 0; s < g.n_scales; ++s) {
         ta.r2[2 * s] = g.s[s].r2_orient;
         ta.off[2 * s] = g.s[s].off_orient;
+        ta.k[2 * s] = g.s[s].k_orient;
         ta.r2[2 * s + 1] = g.s[s].r2_desc;
         ta.off[2 * s + 1] = g.s[s].off_desc;
+        ta.k[2 * s + 1] = g.s[s].k_desc;
     }
     hipLaunchKernelGGL(disc_tables_kernel, dim3(ta.n_tables), dim3(kTabThreads), 0, stream, ta,
                        tables);
