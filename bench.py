@@ -763,17 +763,20 @@ def bench_learned(args, dev, pairs):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1000.0 / steps, eager_ms
 
-    out = {}
-    for name, weights in (("plain", None), ("learned", w)):
-        bp = L.BatchPath(imgs, P, weights=weights)
+    def run(weights, num=3, den=10):
+        bp = L.BatchPath(imgs, P, weights=weights, num=num, den=den)
         g_ms, e_ms = timed_path(bp)
-        out[name] = (g_ms, bp.results(), e_ms)
+        res = bp.results()
         del bp
+        return g_ms, res, e_ms
+
+    out = {"plain": run(None), "learned": run(w)}
     torch.cuda.empty_cache()
     rows, kept = [], []
     t0 = time.perf_counter()
+    plain = [L.finish(out["plain"][1][k], seed=k, H_true=p.H) for k, p in enumerate(pairs)]
     for k, p in enumerate(pairs):
-        pl = L.finish(out["plain"][1][k], seed=k, H_true=p.H)
+        pl = plain[k]
         le = L.finish(out["learned"][1][k], seed=k, H_true=p.H)
         fb = L.needs_fallback(le)
         if fb:
@@ -786,6 +789,23 @@ def bench_learned(args, dev, pairs):
     kept = np.array(kept, dtype=np.float64)          # [pairs, 2]: kept, plain inliers
     per_pair = kept[:, 0] / np.maximum(kept[:, 1], 1)
     ms_p, ms_l = out["plain"][0], out["learned"][0]
+
+    # the same measurement at larger keep fractions (retention against cost)
+    curve = []
+    for num, den in ((7, 20), (2, 5)):
+        g_ms, res, _ = run(w, num, den)
+        kk = []
+        for k, p in enumerate(pairs):
+            le = L.finish(res[k], seed=k)
+            kk.append(L.inlier_retention(plain[k], plain[k] if L.needs_fallback(le) else le))
+        kk = np.array(kk, dtype=np.float64)
+        curve.append({"keep": f"{num}/{den}", "learned_pairs_per_s": round(len(pairs) * 1000.0 / g_ms, 2),
+                      "speedup": round(ms_p / g_ms, 2),
+                      "inlier_retention": round(float(kk[:, 0].sum() / max(kk[:, 1].sum(), 1)), 4),
+                      "inlier_retention_min_pair":
+                          round(float((kk[:, 0] / np.maximum(kk[:, 1], 1)).min()), 4)})
+        del res
+        torch.cuda.empty_cache()
     return {"workload": f"{len(pairs)} mixed-size pairs (widths 1024-4000, 4:3, blob texture, "
                         f"random similarity, IoU 0.3-0.5), L 16/32/64/128; learned path keeps "
                         f"ceil(0.3 n) keypoints per image by scorer logit",
@@ -810,6 +830,9 @@ def bench_learned(args, dev, pairs):
             "fallbacks": int(r[:, 4].sum()),
             "matches_plain": int(r[:, 5].sum()), "matches_learned": int(r[:, 6].sum()),
             "host_ransac_ms_per_pair": round(1000.0 * t_host, 2),
+            "ransac": f"{L.RANSAC_ITERS} hypotheses per pair, then least-squares rounds over the "
+                      f"inliers until the inlier set is unchanged (at most {L.REFINE_ROUNDS})",
+            "keep_curve": curve,
             "weights_sha256": info["sha256"][:16]}
 
 

@@ -509,6 +509,26 @@ int lpsift_ransac_host(const double* xyA, const double* xyB, int64_t n, const in
                        int32_t n_iter, double thresh, double* H, uint8_t* mask,
                        int64_t* n_inliers, int32_t* best_iter);
 
+/* Local optimisation of a homography estimate (a reading: the paper fits
+ * Eq. 7 by RANSAC and leaves the refinement of the winning model open; one
+ * least-squares step over the inliers, as lpsift_ransac_host takes, still
+ * depends on which sample won). On the host in FP64, no GPU involvement.
+ *  xyA, xyB    host arrays of n (x, y) pairs, as for lpsift_ransac_host
+ *  thresh      inlier iff |H a - b| < thresh (px), as for lpsift_ransac_host
+ *  max_rounds  0 .. 1000 least-squares rounds at most
+ *  H           host double[9], row-major: the start (finite), then the result
+ * A round fits H by least squares (h33 = 1, Hartley coordinates, the same
+ * solve as lpsift_ransac_host's refinement) to the inliers of the current H;
+ * the rounds stop when a round leaves the inlier set unchanged, when fewer
+ * than 4 inliers remain, when the solve is singular (H then stays the last
+ * good one), or after max_rounds. Outputs: H, mask (host uint8[n], the
+ * inliers of the final H), *n_inliers, *rounds (rounds taken; 0 leaves H
+ * unchanged and gives its inliers). Errors: EINVAL (null pointer, negative
+ * size, thresh not positive, max_rounds out of range, H not finite). */
+int lpsift_refine_host(const double* xyA, const double* xyB, int64_t n, double thresh,
+                       int32_t max_rounds, double* H, uint8_t* mask, int64_t* n_inliers,
+                       int32_t* rounds);
+
 #ifdef __cplusplus
 }
 #endif

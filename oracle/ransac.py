@@ -18,8 +18,15 @@ used by the product's lpsift_ransac_host):
   * the best hypothesis has the most inliers (earliest on ties); H is then
     re-estimated by linear least squares (h33 = 1, Hartley coordinates) over
     its inliers, and the returned mask is the inlier set of that final H.
+Refinement to a fixed point (reading, also the product's lpsift_refine_host:
+the paper leaves the refinement of the winning model open): from a given H,
+repeat the least-squares fit over the inliers of the current H until the fit
+leaves the inlier set unchanged, fewer than 4 inliers remain, or the round
+limit is reached.
 Pins: exact correspondences recover H to ~1e-12; planted inliers among random
-outliers are all recovered; degenerate samples are skipped.
+outliers are all recovered; degenerate samples are skipped; refinement from a
+perturbed start recovers the planted H and exactly the planted inliers, and
+its result is a fixed point (a second call changes nothing).
 """
 from __future__ import annotations
 
@@ -124,3 +131,26 @@ def ransac(pa: np.ndarray, pb: np.ndarray, samples: np.ndarray, thresh: float = 
     H = dlt(pa[inl], pb[inl]) if inl.sum() >= 4 else H0
     mask = reprojection_error(H, pa, pb) < thresh
     return H, mask, best
+
+
+def refine(pa: np.ndarray, pb: np.ndarray, H: np.ndarray, thresh: float = 3.0,
+           max_rounds: int = 20):
+    """Least-squares rounds from H over the inliers of the current H, until
+    the inlier set stops changing. Returns (H, inlier mask, rounds taken)."""
+    pa = np.asarray(pa, np.float64)
+    pb = np.asarray(pb, np.float64)
+    H = np.asarray(H, np.float64).reshape(3, 3)
+    mask = reprojection_error(H, pa, pb) < thresh
+    rounds = 0
+    while rounds < max_rounds and mask.sum() >= 4:
+        F = dlt(pa[mask], pb[mask])
+        if not np.all(np.isfinite(F)):
+            break
+        rounds += 1
+        H = F
+        new = reprojection_error(H, pa, pb) < thresh
+        done = bool(np.array_equal(new, mask))
+        mask = new
+        if done:
+            break
+    return H, mask, rounds

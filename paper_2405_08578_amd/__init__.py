@@ -65,7 +65,7 @@ EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lp
            "lpsift_match_u8_workspace_size", "lpsift_match_u8",
            "lpsift_describe_multi_workspace_size", "lpsift_describe_multi",
            "lpsift_warp_blend", "lpsift_probe_out_size", "lpsift_probe_ops", "lpsift_probe",
-           "lpsift_quantize_lowp", "lpsift_match_noalloc")
+           "lpsift_quantize_lowp", "lpsift_match_noalloc", "lpsift_refine_host")
 
 _lib = None
 
@@ -166,6 +166,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lpsift_probe.restype = ctypes.c_int
     lib.lpsift_probe.argtypes = [c_i32, c_i64, c_vp, c_vp]
     lib.lpsift_ransac_host.restype = ctypes.c_int
+    lib.lpsift_refine_host.restype = ctypes.c_int
+    lib.lpsift_refine_host.argtypes = [c_vp, c_vp, c_i64, c_f64, c_i32, c_vp, c_vp, c_vp, c_vp]
     lib.lpsift_ransac_host.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp,
                                        P(c_i64), P(c_i32)]
     _lib = lib
@@ -789,3 +791,21 @@ def ransac(xyA, xyB, samples, thresh: float = 3.0):
         a.ctypes.data, b.ctypes.data, len(a), smp.ctypes.data, len(smp), float(thresh),
         H.ctypes.data, mask.ctypes.data, ctypes.byref(n_in), ctypes.byref(best)))
     return (H.reshape(3, 3) if best.value >= 0 else None), mask.astype(bool), best.value
+
+
+def refine_homography(xyA, xyB, H, thresh: float = 3.0, max_rounds: int = 20):
+    """Least-squares rounds over the inliers of H until the inlier set stops
+    changing (host, FP64). Returns (H [3, 3], inlier mask [n] bool, rounds)."""
+    import numpy as np
+    lib = load()
+    a = np.ascontiguousarray(xyA, dtype=np.float64).reshape(-1, 2)
+    b = np.ascontiguousarray(xyB, dtype=np.float64).reshape(-1, 2)
+    if a.shape != b.shape:
+        raise ValueError("xyA and xyB must have the same shape")
+    G = np.ascontiguousarray(H, dtype=np.float64).reshape(9).copy()
+    mask = np.zeros(len(a), np.uint8)
+    n_in, rounds = c_i64(), c_i32()
+    _check("lpsift_refine_host", lib.lpsift_refine_host(
+        a.ctypes.data, b.ctypes.data, len(a), float(thresh), int(max_rounds), G.ctypes.data,
+        mask.ctypes.data, ctypes.byref(n_in), ctypes.byref(rounds)))
+    return G.reshape(3, 3), mask.astype(bool), rounds.value

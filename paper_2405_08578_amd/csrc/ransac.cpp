@@ -8,6 +8,10 @@
 // inliers (normal equations, 8 unknowns, Hartley coordinates) and the final
 // mask is the inlier set of the refined H. The random draws are an input
 // (an [n_iter][4] index array) so that runs are reproducible.
+//
+// lpsift_refine_host repeats that least-squares step from a given H until the
+// inlier set stops changing (a local optimisation of the estimate, so that the
+// final inliers depend on the data rather than on which sample won).
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -189,5 +193,45 @@ extern "C" int lpsift_ransac_host(const double* xyA, const double* xyB, int64_t 
     }
     std::memcpy(H, F, sizeof F);
     *n_inliers = cnt;
+    return LPSIFT_OK;
+}
+
+extern "C" int lpsift_refine_host(const double* xyA, const double* xyB, int64_t n, double thresh,
+                                  int32_t max_rounds, double* H, uint8_t* mask,
+                                  int64_t* n_inliers, int32_t* rounds)
+{
+    if (n < 0 || !H || !n_inliers || !rounds) return LPSIFT_EINVAL;
+    if (!(thresh > 0.0) || !std::isfinite(thresh)) return LPSIFT_EINVAL;
+    if (max_rounds < 0 || max_rounds > 1000) return LPSIFT_EINVAL;
+    if (n > 0 && (!xyA || !xyB || !mask)) return LPSIFT_EINVAL;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(H[i])) return LPSIFT_EINVAL;
+
+    // inliers of the starting H
+    std::vector<int64_t> in;
+    for (int64_t i = 0; i < n; ++i) {
+        mask[i] = inlier(H, xyA, xyB, i, thresh) ? 1 : 0;
+        if (mask[i]) in.push_back(i);
+    }
+    int32_t r = 0;
+    while (r < max_rounds && in.size() >= 4) {
+        double F[9];
+        if (!dlt(xyA, xyB, in.data(), (int64_t)in.size(), F)) break;
+        ++r;
+        std::memcpy(H, F, sizeof F);
+        // the inlier set of the new H; stop once it equals the one it was fitted to
+        std::vector<int64_t> next;
+        bool same = true;
+        for (int64_t i = 0; i < n; ++i) {
+            const uint8_t m = inlier(H, xyA, xyB, i, thresh) ? 1 : 0;
+            same = same && (m == mask[i]);
+            mask[i] = m;
+            if (m) next.push_back(i);
+        }
+        in.swap(next);
+        if (same) break;
+    }
+    *n_inliers = (int64_t)in.size();
+    *rounds = r;
     return LPSIFT_OK;
 }

@@ -111,3 +111,65 @@ def test_ransac_skips_invalid_rows():
     Hr, mask, best = R.ransac(pa, pb, samples)
     assert best == 1 and mask.all()
     assert np.allclose(Hr, H / H[2, 2], atol=1e-9)
+
+
+def shifted(H, dx, dy, deg=0.0):
+    """H followed by a small rotation about the origin and a shift (px)."""
+    c, s = np.cos(np.radians(deg)), np.sin(np.radians(deg))
+    return np.array([[c, -s, dx], [s, c, dy], [0, 0, 1.0]]) @ H
+
+
+def planted(seed, n_in=60, n_out=140, noise=0.0):
+    rng = np.random.default_rng(40 + seed)
+    H = rand_h(rng)
+    pa = rng.uniform(0, 2000, (n_in + n_out, 2))
+    pb = synth.apply_h(H, pa)
+    if noise > 0:
+        pb[:n_in] += rng.normal(0, noise, (n_in, 2))
+    pb[n_in:] = rng.uniform(-500, 2500, (n_out, 2))
+    truth = np.arange(n_in + n_out) < n_in
+    return H / H[2, 2], pa, pb, truth
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_refine_exact_points_give_the_planted_h(seed):
+    # exact inliers: one least-squares round over any >= 4 of them is H itself
+    H, pa, pb, truth = planted(seed)
+    start = shifted(H, 1.0, -0.5)
+    G, mask, rounds = R.refine(pa, pb, start, 3.0)
+    assert np.array_equal(mask, truth)
+    assert np.allclose(G, H, rtol=1e-9, atol=1e-9)
+    assert rounds in (1, 2)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_refine_iterates_until_the_inlier_set_is_stable(seed):
+    # a start 2.9 px off leaves part of the planted inliers out; the first fit
+    # brings them in, so a second round is needed to see the set unchanged
+    H, pa, pb, truth = planted(seed, noise=0.3)
+    start = shifted(H, 2.9, 0.0)
+    m0 = R.reprojection_error(start, pa, pb) < 3.0
+    assert m0[truth].mean() < 0.7
+    G, mask, rounds = R.refine(pa, pb, start, 3.0)
+    assert rounds >= 2
+    assert np.array_equal(mask, truth)
+    corners = np.array([[0, 0], [2000, 0], [2000, 2000], [0, 2000.0]])
+    assert np.abs(synth.apply_h(G, corners) - synth.apply_h(H, corners)).max() < 0.5
+    # the result is a fixed point: one more call takes one round and keeps it
+    G2, mask2, rounds2 = R.refine(pa, pb, G, 3.0)
+    assert rounds2 == 1 and np.array_equal(mask2, mask)
+    assert np.abs(synth.apply_h(G2, corners) - synth.apply_h(G, corners)).max() < 1e-9
+    # a single round stops early, with the first fit's inliers
+    G1, mask1, r1 = R.refine(pa, pb, start, 3.0, max_rounds=1)
+    assert r1 == 1 and np.array_equal(mask1, R.reprojection_error(G1, pa, pb) < 3.0)
+
+
+def test_refine_zero_rounds_and_too_few_inliers():
+    H, pa, pb, truth = planted(0, noise=0.3)
+    start = shifted(H, 1.0, 1.0)
+    G, mask, rounds = R.refine(pa, pb, start, 3.0, max_rounds=0)
+    assert rounds == 0 and np.array_equal(G, start)
+    assert np.array_equal(mask, R.reprojection_error(start, pa, pb) < 3.0)
+    far = shifted(H, 400.0, 0.0)
+    G, mask, rounds = R.refine(pa, pb, far, 3.0)
+    assert mask.sum() < 4 and rounds == 0 and np.array_equal(G, far)

@@ -55,3 +55,43 @@ def test_rejects_bad_arguments():
         lp.ransac(pa, pb, np.array([[0, 1, 2, len(pa)]]))       # index out of range
     with pytest.raises(lp.LpsiftError):
         lp.ransac(pa, pb, np.array([[0, 1, 2, 3]]), thresh=0.0)
+
+
+def shifted(H, dx, dy):
+    return np.array([[1, 0, dx], [0, 1, dy], [0, 0, 1.0]]) @ H
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_refinement_matches_oracle(seed):
+    pa, pb = problem(seed)
+    samples = synth.ransac_samples(len(pa), 500, np.random.default_rng(100 + seed))
+    Ho, _, _ = R.ransac(pa, pb, samples, 3.0)
+    corners = np.array([[0, 0], [2600, 0], [2600, 1600], [0, 1600.0]])
+    for start in (Ho, shifted(Ho, 2.5, -1.0)):
+        Go, mo, ro = R.refine(pa, pb, start, 3.0)
+        Gl, ml, rl = lp.refine_homography(pa, pb, start, 3.0)
+        assert rl == ro
+        safe = np.abs(R.reprojection_error(Go, pa, pb) - 3.0) > 1e-6
+        assert np.array_equal(ml[safe], mo[safe])
+        assert np.abs(synth.apply_h(Gl, corners) - synth.apply_h(Go, corners)).max() < 1e-6
+
+
+def test_refinement_edge_cases():
+    pa, pb = problem(3)
+    samples = synth.ransac_samples(len(pa), 500, np.random.default_rng(103))
+    Ho, _, _ = R.ransac(pa, pb, samples, 3.0)
+    G, m, r = lp.refine_homography(pa, pb, Ho, 3.0, max_rounds=0)
+    assert r == 0 and np.array_equal(G, Ho)
+    assert np.array_equal(m, R.reprojection_error(Ho, pa, pb) < 3.0)
+    G, m, r = lp.refine_homography(pa, pb, shifted(Ho, 500.0, 0.0), 3.0)
+    assert r == 0 and m.sum() < 4
+    G, m, r = lp.refine_homography(np.zeros((0, 2)), np.zeros((0, 2)), np.eye(3))
+    assert r == 0 and len(m) == 0
+    with pytest.raises(lp.LpsiftError):
+        lp.refine_homography(pa, pb, Ho, thresh=0.0)
+    with pytest.raises(lp.LpsiftError):
+        lp.refine_homography(pa, pb, Ho, max_rounds=-1)
+    bad = Ho.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(lp.LpsiftError):
+        lp.refine_homography(pa, pb, bad)
