@@ -51,7 +51,9 @@ int make_geometry(const lpsift_params* p, Geometry* g)
         entries += G.n_orient;
         G.off_desc = entries;
         G.n_desc = disc_count(G.r2_desc);
-        entries += G.n_desc;
+        G.n_buckets = G.n_desc <= kBucketMaxEntries ? kDescBuckets : 1;
+        G.cap_desc = G.n_desc;
+        entries += G.n_buckets * G.cap_desc;
     }
     g->table_entries = entries;
     return LPSIFT_OK;

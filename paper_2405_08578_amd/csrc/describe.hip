@@ -2,10 +2,12 @@
 // (Sec. 2.3, Eq. 3-5).
 //
 // Three kernels, all enqueued by launch_describe:
-//  1. disc_tables_kernel: for every scale, the integer offsets of the
-//     orientation disc (radius round(1.5 w_s)) and of the descriptor disc
-//     (radius w_s sqrt(2) (d+1)/2, which circumscribes the rotated d+1 cell
-//     square where trilinear weights can be non-zero), row-major.
+//  1. disc tables (built by the first polar_field_kernel launch): for every
+//     scale, the offsets of the orientation disc (radius round(1.5 w_s)),
+//     row-major, and of the descriptor disc (radius w_s sqrt(2) (d+1)/2,
+//     which circumscribes the rotated d+1 cell square where trilinear weights
+//     can be non-zero), once per bucket of 64 orientation buckets, keeping
+//     the entries that the rotated square can reach for an angle of the bucket.
 //  2. polar_field_kernel: the Eq. 5 gradient of every pixel once, as
 //     (magnitude, angle in turns in [0, 1)); border pixels get magnitude 0.
 //     Each image pixel is visited by ~10 keypoint supports, so the atan2 and
@@ -43,10 +45,16 @@ constexpr size_t kFieldGroupBytes = 128u << 20;
 // ---------------------------------------------------------------- tables --
 
 struct TableArgs {
-    int32_t n_tables;
-    int32_t r2[2 * LPSIFT_MAX_SCALES];
-    int32_t off[2 * LPSIFT_MAX_SCALES];
-    float k[2 * LPSIFT_MAX_SCALES];   // Gaussian exponent factor of the table
+    int32_t n_scales;
+    int32_t r2_orient[LPSIFT_MAX_SCALES];
+    int32_t off_orient[LPSIFT_MAX_SCALES];
+    float k_orient[LPSIFT_MAX_SCALES];     // Gaussian exponent factor of the table
+    int32_t r2_desc[LPSIFT_MAX_SCALES];
+    int32_t off_desc[LPSIFT_MAX_SCALES];
+    int32_t cap_desc[LPSIFT_MAX_SCALES];
+    int32_t n_buckets[LPSIFT_MAX_SCALES];
+    float k_desc[LPSIFT_MAX_SCALES];
+    double inv_ws[LPSIFT_MAX_SCALES];
 };
 
 __device__ inline int32_t pack_offset(int dx, int dy)
@@ -65,40 +73,133 @@ __device__ inline float4 disc_entry(int dx, int dy, float k)
                        __int_as_float(pack_offset(dx, dy)));
 }
 
-constexpr int kTabThreads = 256;
-
-// One workgroup per table. Thread t owns a contiguous run of rows; a block
-// scan of the per-thread entry counts gives every row its start.
-__global__ __launch_bounds__(kTabThreads) void disc_tables_kernel(TableArgs a, float4* tables)
+// Whether offset (dx, dy) can fall in the square |u|, |v| < 2.5 of reachable
+// subregions for some angle of an orientation bucket of nb (angles in
+// [b, b + 1) / nb turns). (c, s) = (cos, sin) of the bucket's centre angle,
+// divided by w_s: the offset rotates there to (u, v), in subregions; within
+// the bucket the angle differs by at most pi / nb, which moves each
+// coordinate by at most r pi / nb (r = the offset's length in subregions).
+// The margin takes 1 % more and 1e-3 subregions for the rounding of this test
+// and of the visit's own rotation, so the bucket keeps every entry that a
+// visit's test can accept.
+__device__ inline bool in_bucket(int dx, int dy, float c, float s, float inv_ws, float slack)
 {
-    __shared__ int scan[kTabThreads];
-    const int t = blockIdx.x, tid = threadIdx.x;
-    const int r2 = a.r2[t];
+    const float fx = (float)dx, fy = (float)dy;
+    const float u = fmaf(c, fx, s * fy), v = fmaf(c, fy, -(s * fx));
+    const float m = fmaf(sqrtf(fmaf(fx, fx, fy * fy)) * inv_ws, slack, 2.5f + 1e-3f);
+    return fabsf(u) < m && fabsf(v) < m;
+}
+
+constexpr int kTabThreads = 256;
+constexpr int kTabMaxRows = 4001;   // 2 R + 1 rows, R <= 2000 (support radius limit)
+static_assert(kBucketMaxEntries <= 32 * kTabThreads, "a thread's run of a bucketed disc fits a 32-bit mask");
+
+// Inclusive scan of one value per thread over the workgroup (Hillis-Steele).
+__device__ inline int block_scan(int* scan, int v)
+{
+    const int tid = threadIdx.x;
+    scan[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kTabThreads; off <<= 1) {
+        const int u = (tid >= off) ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += u;
+        __syncthreads();
+    }
+    const int r = scan[tid];
+    __syncthreads();
+    return r;
+}
+
+// Table job (j, s) of one workgroup: j = 0 the orientation disc of scale s,
+// j = 1 + b bucket b of its descriptor disc. The disc's entries, in row-major order, are split
+// into 256 contiguous runs, one per thread (at most 32 entries each when the
+// disc is bucketed); a thread marks the entries of its run that the bucket
+// keeps, and a block scan of the marked counts gives every run its output
+// start, so the list stays in row-major order. The entry count of each
+// descriptor bucket goes to counts[s kDescBuckets + b].
+__device__ void build_table(const TableArgs& a, float4* tables, int32_t* counts, int j, int s,
+                            int* scan, int* row_start)
+{
+    const int tid = threadIdx.x;
+    const bool orient = j == 0;
+    const int b = j - 1;
+    if (!orient && b >= a.n_buckets[s]) return;
+    const int r2 = orient ? a.r2_orient[s] : a.r2_desc[s];
+    const int nb = orient ? 1 : a.n_buckets[s];
     const int R = isqrt_floor(r2);
     const int rows = 2 * R + 1;
-    const int per = (rows + kTabThreads - 1) / kTabThreads;
-    const int row0 = tid * per;
-    int cnt = 0;
-    for (int i = row0; i < row0 + per && i < rows; ++i) {
-        const int dy = i - R;
-        cnt += 2 * isqrt_floor(r2 - dy * dy) + 1;
-    }
-    scan[tid] = cnt;
-    __syncthreads();
-    for (int off = 1; off < kTabThreads; off <<= 1) {   // inclusive Hillis-Steele scan
-        const int v = (tid >= off) ? scan[tid - off] : 0;
+
+    // row starts: thread t sums a contiguous run of rows, a block scan places them
+    {
+        const int per = (rows + kTabThreads - 1) / kTabThreads;
+        const int i0 = tid * per, i1 = min(i0 + per, rows);
+        int c = 0;
+        for (int i = i0; i < i1; ++i) c += 2 * isqrt_floor(r2 - (i - R) * (i - R)) + 1;
+        int at = block_scan(scan, c) - c;
+        for (int i = i0; i < i1; ++i) {
+            row_start[i] = at;
+            at += 2 * isqrt_floor(r2 - (i - R) * (i - R)) + 1;
+        }
+        if (tid == kTabThreads - 1) row_start[rows] = at;
         __syncthreads();
-        scan[tid] += v;
-        __syncthreads();
     }
-    int start = scan[tid] - cnt;
-    float4* out = tables + a.off[t];
-    const float k = a.k[t];
-    for (int i = row0; i < row0 + per && i < rows; ++i) {
-        const int dy = i - R;
-        const int hw = isqrt_floor(r2 - dy * dy);
-        for (int dx = -hw; dx <= hw; ++dx) out[start++] = disc_entry(dx, dy, k);
+    const int n = row_start[rows];
+    const int per = (n + kTabThreads - 1) / kTabThreads;
+    const int j0 = min(tid * per, n), j1 = min(j0 + per, n);
+    // the row of entry j0: the last row starting at or before it
+    int lo = 0, hi = rows - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_start[mid] <= j0) lo = mid; else hi = mid - 1;
     }
+    const int i_first = lo;
+    const int dy_first = i_first - R;
+    const int hw_first = isqrt_floor(r2 - dy_first * dy_first);
+    const int dx_first = -hw_first + (j0 - row_start[i_first]);
+
+    // (cos, sin) of the bucket's centre angle over w_s, and the slack
+    // (single precision: its error is far inside the 1e-3 margin)
+    const float th = 6.2831853f * ((float)b + 0.5f) / (float)nb;
+    const float inv_ws = (float)a.inv_ws[s];
+    float sn, c;
+    sincosf(th, &sn, &c);
+    c *= inv_ws;
+    sn *= inv_ws;
+    const float slack = (float)(3.141592653589793 / nb * 1.01);
+    const bool filter = nb > 1;   // bucketed discs have at most 8,192 entries: per <= 32
+
+    unsigned keep = 0u;
+    int cnt = j1 - j0;
+    if (filter) {
+        int dx = dx_first, dy = dy_first, hw = hw_first;
+        for (int k = 0; k < j1 - j0; ++k) {
+            if (in_bucket(dx, dy, c, sn, inv_ws, slack)) keep |= 1u << k;
+            if (++dx > hw) {
+                ++dy;
+                hw = isqrt_floor(r2 - dy * dy);
+                dx = -hw;
+            }
+        }
+        cnt = __popc(keep);
+    }
+    const int total = block_scan(scan, cnt);
+    int at = total - cnt;
+    float4* out = tables + (orient ? (int64_t)a.off_orient[s]
+                                   : (int64_t)a.off_desc[s] + (int64_t)b * a.cap_desc[s]);
+    const float k = orient ? a.k_orient[s] : a.k_desc[s];
+    {
+        int dx = dx_first, dy = dy_first, hw = hw_first;
+        for (int e = 0; e < j1 - j0; ++e) {
+            if (!filter || ((keep >> e) & 1u)) out[at++] = disc_entry(dx, dy, k);
+            if (++dx > hw) {
+                ++dy;
+                hw = isqrt_floor(r2 - dy * dy);
+                dx = -hw;
+            }
+        }
+    }
+    if (!orient && tid == kTabThreads - 1) counts[s * kDescBuckets + b] = total;
 }
 
 // ---------------------------------------------------------- gradient field --
@@ -115,12 +216,29 @@ struct FieldArgs {
     FieldImg img[kDescBatch];
 };
 
-// grid: (ceil(w/256), h, image); one row segment of 256 pixels per workgroup.
-__global__ __launch_bounds__(256) void polar_field_kernel(FieldArgs a)
+// One launch builds the disc tables and the gradient fields: workgroups
+// 0 .. n_table - 1 take the table jobs (dispatched first, so the few long
+// table jobs run beside the many short field rows instead of after them);
+// workgroup n_table + (z gy + y) gx + x then takes the row segment of 256
+// pixels at column 256 x of row y of image z.
+__global__ __launch_bounds__(256) void polar_field_kernel(FieldArgs a, TableArgs ta,
+                                                          float4* tables, int32_t* counts,
+                                                          int n_table, int gx, int gy)
 {
-    const FieldImg& I = a.img[blockIdx.z];
-    const int r = blockIdx.y;
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    static_assert(kTabThreads == 256, "table jobs run on the field kernel's workgroups");
+    __shared__ int scan[kTabThreads];
+    __shared__ int row_start[kTabMaxRows + 1];
+    const int blk = (int)blockIdx.x;
+    if (blk < n_table) {
+        build_table(ta, tables, counts, blk % (1 + kDescBuckets), blk / (1 + kDescBuckets), scan,
+                    row_start);
+        return;
+    }
+    const int f = blk - n_table;
+    const int z = f / (gx * gy), rem = f - z * (gx * gy);
+    const FieldImg& I = a.img[z];
+    const int r = rem / gx;
+    const int c = (rem - r * gx) * 256 + threadIdx.x;
     if (r >= I.h || c >= I.w) return;
     float2 out = make_float2(0.0f, 0.0f);
     if (r >= 1 && r <= I.h - 2 && c >= 1 && c <= I.w - 2) {
@@ -165,6 +283,7 @@ struct DescArgs {   // passed by value: keep well under 4 KB
     int32_t first_scale;   // orient_describe_kernel: scales first_scale .. n_scales - 1
     int32_t half_scales;   // orient_describe_half_kernel: scales 0 .. half_scales - 1
     float peak_ratio;      // and its secondary-peak threshold
+    const int32_t* bcount; // entries of descriptor bucket b of scale s at [s kDescBuckets + b]
     ScaleGeom geom[LPSIFT_MAX_SCALES];
     int32_t L[LPSIFT_MAX_SCALES];
     // first slot of scale s in image i
@@ -377,15 +496,17 @@ template <int kStride, int kC = kCopies>
 __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bool live, int kx,
                                            int ky, const float2* field, int W, int H,
                                            const ScaleGeom& G, const float4* tables,
-                                           float th_turns)
+                                           const int32_t* bcount, float th_turns)
 {
     float sn, cs;
     sn = __builtin_amdgcn_sinf(th_turns);   // v_sin_f32 / v_cos_f32 take revolutions
     cs = __builtin_amdgcn_cosf(th_turns);
     const float ca = cs * G.inv_ws, sa = sn * G.inv_ws;   // rotation by -theta, in cells
-    const int nd = live ? G.n_desc : 0;
+    // the bucket of theta (any angle, wrapped to [0, 1) turns by the mask)
+    const int bk = G.n_buckets > 1 ? ((int)floorf(th_turns * (float)kDescBuckets) & (kDescBuckets - 1)) : 0;
+    const int nd = live ? bcount[bk] : 0;
     const int perd = (nd + kStride - 1) / kStride;
-    const float4* tabd = tables + G.off_desc;
+    const float4* tabd = tables + G.off_desc + (int64_t)bk * G.cap_desc;
     unsigned long long* hv = hist + (sub % kC) * kBins;   // this lane's copy
     for (int it0 = 0; it0 < perd; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
@@ -451,9 +572,10 @@ template <bool kWaveOnly, int kC>
 __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, bool live, int kx,
                                             int ky, const float2* field, int W, int H,
                                             const ScaleGeom& G, const float4* tables,
-                                            float th_turns, float& r0, float& r1)
+                                            const int32_t* bcount, float th_turns, float& r0,
+                                            float& r1)
 {
-    desc_votes<64, kC>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns);
+    desc_votes<64, kC>(hist, lane, live, kx, ky, field, W, H, G, tables, bcount, th_turns);
     hist_sync<kWaveOnly>();
     const float dinv = kVoteInv;
     unsigned long long s0 = 0ull, s1 = 0ull;
@@ -550,7 +672,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             if (live && lane == 0) I.theta[out_at] = th_turns * 6.283185307179586f;
             // ---- descriptor histogram: 4 x 4 cells x 8 directions ----
             float r0, r1;
-            describe_at<true, kC>(hist, lane, live, kx, ky, field, W, H, G, tables, th_turns, r0, r1);
+            describe_at<true, kC>(hist, lane, live, kx, ky, field, W, H, G, tables,
+                                  a.bcount + sc * kDescBuckets, th_turns, r0, r1);
             if (live) {
                 float* out = I.desc + out_at * 128;
                 out[lane] = r0;
@@ -599,7 +722,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         }
         const float th = I.obuf[slot * kMaxOrient + m];
         float r0, r1;
-        describe_at<true, kC>(hist, lane, true, kx, ky, field, W, H, G, tables, th, r0, r1);
+        describe_at<true, kC>(hist, lane, true, kx, ky, field, W, H, G, tables,
+                              a.bcount + sc * kDescBuckets, th, r0, r1);
         const int64_t row = row0 + m;
         float* out = I.desc + row * 128;
         out[lane] = r0;
@@ -717,7 +841,8 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     // The norms add (e, e + 64) pairs first, then the halves, then butterflies
     // over 32 lanes: the summation tree of wave_sum in the whole-wave kernel,
     // so both kernels give bit-identical descriptors.
-    desc_votes<32, kHalfCopies>(hist, sub, live, kx, ky, field, W, H, G, tables, th_turns);
+    desc_votes<32, kHalfCopies>(hist, sub, live, kx, ky, field, W, H, G, tables,
+                                a.bcount + sc * kDescBuckets, th_turns);
     wave_sync();
     float d[4];
 #pragma unroll
@@ -810,9 +935,15 @@ __global__ __launch_bounds__(kScanThreads) void orient_scan_kernel(ScanArgs a)
     if (t == 0) *I.total = carry;
 }
 
-size_t field_offset(const Geometry& g)
+// Workspace: disc tables, then the bucket entry counts, then the fields.
+size_t counts_offset(const Geometry& g)
 {
     return align_up((size_t)g.table_entries * sizeof(float4), 256);
+}
+
+size_t field_offset(const Geometry& g)
+{
+    return counts_offset(g) + align_up((size_t)LPSIFT_MAX_SCALES * kDescBuckets * 4, 256);
 }
 
 }  // namespace
@@ -850,19 +981,23 @@ int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, c
     char* base = static_cast<char*>(ws);
     float4* tables = reinterpret_cast<float4*>(base);
 
+    int32_t* bcount = reinterpret_cast<int32_t*>(base + counts_offset(g));
     TableArgs ta{};
-    ta.n_tables = 2 * g.n_scales;
+    ta.n_scales = g.n_scales;
     for (int s = 0; s < g.n_scales; ++s) {
-        ta.r2[2 * s] = g.s[s].r2_orient;
-        ta.off[2 * s] = g.s[s].off_orient;
-        ta.k[2 * s] = g.s[s].k_orient;
-        ta.r2[2 * s + 1] = g.s[s].r2_desc;
-        ta.off[2 * s + 1] = g.s[s].off_desc;
-        ta.k[2 * s + 1] = g.s[s].k_desc;
+        const ScaleGeom& G = g.s[s];
+        ta.r2_orient[s] = G.r2_orient;
+        ta.off_orient[s] = G.off_orient;
+        ta.k_orient[s] = G.k_orient;
+        ta.r2_desc[s] = G.r2_desc;
+        ta.off_desc[s] = G.off_desc;
+        ta.cap_desc[s] = G.cap_desc;
+        ta.n_buckets[s] = G.n_buckets;
+        ta.k_desc[s] = G.k_desc;
+        ta.inv_ws[s] = 1.0 / (double)G.ws;
     }
-    hipLaunchKernelGGL(disc_tables_kernel, dim3(ta.n_tables), dim3(kTabThreads), 0, stream, ta,
-                       tables);
-    if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
+    // the tables are built by the first field launch (n_table workgroups)
+    int n_table = (1 + kDescBuckets) * g.n_scales;
 
     size_t foff = field_offset(g);
     size_t moff = describe_workspace_bytes(imgs, n, g);   // multi buffers follow the fields
@@ -912,14 +1047,18 @@ int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, c
         }
         {
             TimedScope ts(LPSIFT_KERNEL_GRADIENT, stream);
-            hipLaunchKernelGGL(polar_field_kernel, dim3((maxw + 255) / 256, maxh, nb), dim3(256), 0,
-                               stream, fa);
+            const int gx = (maxw + 255) / 256;
+            const int64_t blocks = (int64_t)n_table + (int64_t)gx * maxh * nb;
+            hipLaunchKernelGGL(polar_field_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, fa,
+                               ta, tables, bcount, n_table, gx, maxh);
+            n_table = 0;
         }
         if (hipGetLastError() != hipSuccess) return LPSIFT_EHIP;
 
         da.list = sel ? 1 : 0;
         da.max_orient = ms ? ms->max_orient : 1;
         da.peak_ratio = ms ? ms->peak_ratio : 1.0f;
+        da.bcount = bcount;
         // per-XCD band lists; the grid covers the longest one
         int64_t longest = 0;
         for (int s = 0; s < g.n_scales; ++s) {

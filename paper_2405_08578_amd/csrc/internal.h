@@ -46,15 +46,24 @@ struct ScaleGeom {
     int r2_desc;       // floor((w_s sqrt(2) (d+1)/2)^2)
     int off_orient;    // entry offset of the orientation disc table
     int n_orient;      // entries of that table
-    int off_desc;      // entry offset of the descriptor disc table
-    int n_desc;
+    int off_desc;      // entry offset of the descriptor tables (bucket b at off_desc + b cap_desc)
+    int n_desc;        // entries of the whole descriptor disc
+    int n_buckets;     // orientation buckets of the descriptor table: kDescBuckets or 1
+    int cap_desc;      // entries reserved per bucket (n_desc)
 };
+
+// The descriptor disc is stored once per orientation bucket, keeping only the
+// entries that the square of reachable subregions can cover for some angle of
+// the bucket (about 27 % fewer visits than the whole disc); discs above
+// kBucketMaxEntries entries are stored whole, as one bucket.
+constexpr int kDescBuckets = 64;
+constexpr int kBucketMaxEntries = 8192;
 
 struct Geometry {
     int n_scales;
     int L[LPSIFT_MAX_SCALES];
     ScaleGeom s[LPSIFT_MAX_SCALES];
-    int table_entries;  // total int32 entries of all disc tables
+    int table_entries;  // total 16-byte entries of all disc tables
 };
 
 // Validated, derived view of lpsift_params. Returns LPSIFT_OK or an error.

@@ -112,9 +112,11 @@ def test_describe_validation_and_workspace(lib):
     P = prm.c()
     ims = (lp.lpsift_image * 2)(image(1600, 2600), image(480, 640))
     need = lib.lpsift_describe_workspace_size(ims, 2, ctypes.byref(P))
-    # the two gradient fields (8 bytes per pixel) dominate
+    # the two gradient fields (8 bytes per pixel) and the disc tables: 16 bytes
+    # per entry, each descriptor disc once per orientation bucket (64 x at most
+    # the 9,436 entries of the four discs at L = 16..128)
     assert need >= 8 * (1600 * 2600 + 480 * 640)
-    assert need < 8 * (1600 * 2600 + 480 * 640) + (1 << 20)
+    assert need < 8 * (1600 * 2600 + 480 * 640) + 16 * (64 * 9436 + 2000) + (1 << 16)
     n0 = lp.num_keypoints(1600, 2600, prm)
     n1 = lp.num_keypoints(480, 640, prm)
     ks = (lp.lpsift_keypoints * 2)(kps(n0), kps(n1))
