@@ -83,6 +83,11 @@ def parse():
     return ap.parse_args()
 
 
+# the autotuner's search: candidate-range splits x wavefronts per FP32 workgroup
+TUNE_CHUNKS = (2, 4, 6, 8, 12, 16)
+TUNE_WAVES = (2, 4, 8)
+
+
 def log(*a):
     """Progress of the run on stderr (the JSON line alone goes to stdout)."""
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -217,13 +222,15 @@ def headline(args, dev, tiles, flush, out):
     torch.cuda.synchronize()
     A = [ap.desc[i] for i, _ in ap.pairs]
     B = [ap.desc[j] for _, j in ap.pairs]
-    tunes = {prec: lp.match_tune(A, B, precision=prec, candidates=(2, 4, 6, 8, 12, 16), reps=1)
+    tunes = {prec: lp.match_tune(A, B, precision=prec, candidates=TUNE_CHUNKS, waves=TUNE_WAVES,
+                                 reps=1)
              for prec in (0, 3)}
-    log("tuned:", {p: t["b_chunks"] for p, t in tunes.items()})
+    log("tuned:", {p: (t["b_chunks"], t["qblock_waves"]) for p, t in tunes.items()})
     del A, B, ap
     torch.cuda.empty_cache()
 
-    ap = AllPairs(imgs, P, precision=0, b_chunks=tunes[0]["b_chunks"])
+    ap = AllPairs(imgs, P, precision=0, b_chunks=tunes[0]["b_chunks"],
+                  qblock_waves=tunes[0]["qblock_waves"])
     ap.capture()
     for _ in range(args.warmup):
         flush()
@@ -333,7 +340,7 @@ def headline(args, dev, tiles, flush, out):
                                "written) before each step",
                    "tiles": [list(t.shape) for t in tiles.images], "pairs": 36, "L": LS,
                    "descriptors": n_slots, "desc_dim": 128,
-                   "b_chunks": tunes[0]["b_chunks"]},
+                   "b_chunks": tunes[0]["b_chunks"], "qblock_waves": tunes[0]["qblock_waves"]},
         "timing": {"cold_ms_per_step": round(ms_per_step, 4),
                    "replay_event_ms_median": round(replay_ms[len(replay_ms) // 2], 4),
                    "replay_event_ms_min_max": [round(replay_ms[0], 4), round(replay_ms[-1], 4)],
@@ -428,7 +435,8 @@ def precision_variants(args, dev, tiles, imgs, P, n_kp, flops, tune, ref_lists, 
     peaks = {3: PEAK_BF16_MFMA, 1: PEAK_BF16_MFMA, 2: PEAK_FP8_MFMA}
     for prec, name in ((3, "split_bf16x3_certified"), (1, "bf16"), (2, "fp8")):
         bc = tune["split"]["b_chunks"] if prec == 3 else 0
-        ap = AllPairs(imgs, P, precision=prec, b_chunks=bc)
+        qw = tune["split"]["qblock_waves"] if prec == 3 else 0
+        ap = AllPairs(imgs, P, precision=prec, b_chunks=bc, qblock_waves=qw)
         ap.capture()
         for _ in range(max(1, args.warmup)):
             ap.replay()
@@ -506,7 +514,8 @@ def registration(args, dev, tiles, imgs, P, tune):
     stream = torch.cuda.current_stream()
     steps = max(2, args.steps // 4)
     u = torch.from_numpy(synth.ransac_uniforms(16384, np.random.default_rng(11))).to(dev)
-    ap = AllPairs(imgs, P, precision=0, b_chunks=tune["fp32"]["b_chunks"], ransac_uniforms=u)
+    ap = AllPairs(imgs, P, precision=0, b_chunks=tune["fp32"]["b_chunks"],
+                  qblock_waves=tune["fp32"]["qblock_waves"], ransac_uniforms=u)
     ap.capture()
     for _ in range(max(1, args.warmup)):
         ap.replay()
@@ -930,10 +939,12 @@ def main():
     ref_lists = [{k: v.cpu().numpy() for k, v in o.items()} for o in ap.out]
     ap_desc = ap.desc
     out["tuning"] = {"fp32_b_chunks": tune["fp32"]["b_chunks"],
+                     "fp32_qblock_waves": tune["fp32"]["qblock_waves"],
                      "split_b_chunks": tune["split"]["b_chunks"],
-                     "candidates": tune["fp32"]["candidates"],
-                     "fp32_ms": [round(v, 2) for v in tune["fp32"]["ms"]],
-                     "split_ms": [round(v, 2) for v in tune["split"]["ms"]]}
+                     "split_qblock_waves": tune["split"]["qblock_waves"],
+                     "candidates": tune["fp32"]["candidates"], "waves": tune["fp32"]["waves"],
+                     "fp32_ms": [[round(v, 2) for v in row] for row in tune["fp32"]["ms"]],
+                     "split_ms": [[round(v, 2) for v in row] for row in tune["split"]["ms"]]}
     if not args.headline_only:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -139,6 +139,9 @@ typedef struct lpsift_keypoints {
  *              finite in FP32 (true of every row lpsift_describe writes);
  *              for other inputs the lists are unspecified.
  *  b_chunks   candidate-range split of the contraction (0 = automatic, <= 16)
+ *  qblock_waves  wavefronts per workgroup of the FP32 contraction (precision 0
+ *              and precision 3's re-match), each holding 64 queries: 0 =
+ *              automatic (4), or 2, 4, 8; every value gives the same lists
  *  stats       optional device pointer to one uint32: after the call (stream
  *              order) it holds the number of queries, summed over all pairs,
  *              that precision 3 re-matched with precision 0 (0 otherwise) */
@@ -147,6 +150,7 @@ typedef struct lpsift_match_params {
     float abs_thresh;
     int32_t precision;
     int32_t b_chunks;
+    int32_t qblock_waves;
     void* stats;
 } lpsift_match_params;
 
@@ -360,21 +364,28 @@ int lpsift_match_noalloc(const float* const* descA, const int64_t* nA,
 int lpsift_quantize_lowp(const float* desc, int64_t n, int32_t precision, void* q, float* scale,
                          void* stream);
 
-/* Autotuner of the candidate-range split of lpsift_match (its b_chunks): for
- * each of n_candidates values (each 1..16) it runs the call once untimed and
- * reps times timed on `stream`, stores the mean milliseconds per call in
- * ms[c] (host array of n_candidates) and the fastest value in *best (host).
- * All other arguments are those of lpsift_match; the workspace must satisfy
- * every candidate (lpsift_match_workspace_size with b_chunks set to it). The
- * outputs hold the last run's lists. Synchronises the stream, so it cannot be
- * captured in a graph. Errors: EINVAL (bad candidate, n_candidates < 1, reps
- * outside 1..1000, null ms/best, or any lpsift_match argument error),
+/* Autotuner of lpsift_match's work split: the candidate-range split
+ * (b_chunks) and, for the FP32 contraction, the wavefronts per workgroup
+ * (qblock_waves; each wavefront holds 64 queries). For each of n_waves wave
+ * counts (0, 2, 4 or 8; n_waves = 0 keeps mp->qblock_waves and ignores
+ * waves / best_waves) and each of n_candidates split values (1..16) it runs
+ * the call once untimed and reps times timed on `stream`, stores the mean
+ * milliseconds per call in ms[w * n_candidates + c] (host array of
+ * max(n_waves, 1) x n_candidates) and the fastest combination in *best and
+ * *best_waves (host). Every combination gives the same lists. All other
+ * arguments are those of lpsift_match; the workspace must satisfy every
+ * combination (lpsift_match_workspace_size with both fields set). The outputs
+ * hold the last run's lists. Synchronises the stream, so it cannot be
+ * captured in a graph. Errors: EINVAL (bad candidate or wave count,
+ * n_candidates < 1, n_waves < 0, reps outside 1..1000, null ms/best, null
+ * waves/best_waves with n_waves > 0, or any lpsift_match argument error),
  * ECAPACITY, EHIP. */
 int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float* const* descB,
                       const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
-                      const int32_t* candidates, int32_t n_candidates, int32_t reps,
-                      void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
-                      float* const* d2, float* ms, int32_t* best, void* stream);
+                      const int32_t* candidates, int32_t n_candidates, const int32_t* waves,
+                      int32_t n_waves, int32_t reps, void* workspace, size_t ws_bytes,
+                      int32_t* const* match, float* const* d1, float* const* d2, float* ms,
+                      int32_t* best, int32_t* best_waves, void* stream);
 
 /* uint8 descriptors, the stored form of SIFT implementations (not fixed by the
  * paper; Sec. 2.3 descriptors are unit-norm FP32 vectors).

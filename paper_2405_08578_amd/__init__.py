@@ -53,7 +53,7 @@ class lpsift_ransac_params(ctypes.Structure):
 
 class lpsift_match_params(ctypes.Structure):
     _fields_ = [("ratio", c_f64), ("abs_thresh", c_f32), ("precision", c_i32),
-                ("b_chunks", c_i32), ("stats", c_vp)]
+                ("b_chunks", c_i32), ("qblock_waves", c_i32), ("stats", c_vp)]
 
 
 EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
@@ -110,9 +110,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                          P(lpsift_match_params), P(c_vp), P(c_vp), P(c_vp), c_vp]
     lib.lpsift_match_tune.restype = ctypes.c_int
     lib.lpsift_match_tune.argtypes = [P(c_vp), P(c_i64), P(c_vp), P(c_i64), c_i32,
-                                      P(lpsift_match_params), P(c_i32), c_i32, c_i32, c_vp,
-                                      ctypes.c_size_t, P(c_vp), P(c_vp), P(c_vp), P(c_f32),
-                                      P(c_i32), c_vp]
+                                      P(lpsift_match_params), P(c_i32), c_i32, P(c_i32), c_i32,
+                                      c_i32, c_vp, ctypes.c_size_t, P(c_vp), P(c_vp), P(c_vp),
+                                      P(c_f32), P(c_i32), P(c_i32), c_vp]
     lib.lpsift_timing_enable.restype = ctypes.c_int
     lib.lpsift_timing_enable.argtypes = [c_i32]
     lib.lpsift_timing_read.restype = ctypes.c_int
@@ -316,12 +316,13 @@ def describe(images, kps, params: Params, workspace=None, theta=None, desc=None,
 
 
 def match_params(ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
-                 b_chunks: int = 0, stats=None) -> lpsift_match_params:
+                 b_chunks: int = 0, stats=None, qblock_waves: int = 0) -> lpsift_match_params:
     mp = lpsift_match_params()
     mp.ratio = ratio
     mp.abs_thresh = abs_thresh
     mp.precision = precision
     mp.b_chunks = b_chunks
+    mp.qblock_waves = qblock_waves
     mp.stats = None if stats is None else stats.data_ptr()
     return mp
 
@@ -365,12 +366,13 @@ def _match_args(descA, descB, out, workspace, need, stream=None):
 
 def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
           b_chunks: int = 0, workspace=None, out=None, stream=None,
-          stats=None) -> List[Dict[str, "object"]]:
+          stats=None, qblock_waves: int = 0) -> List[Dict[str, "object"]]:
     """Nearest neighbour of every row of descA[p] among descB[p] with the ratio
     test, for every pair p. stats: optional int32 CUDA tensor [1] that receives
-    the number of queries the split path re-matched in FP32 (sum over pairs)."""
+    the number of queries the split path re-matched in FP32 (sum over pairs).
+    b_chunks, qblock_waves: the work split (0 = automatic; see match_tune)."""
     lib = load()
-    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats, qblock_waves)
     out, head, tail = _match_args(descA, descB, out, workspace,
                                   lambda nA, nB: match_workspace_size(nA, nB, mp), stream)
     _check("lpsift_match", lib.lpsift_match(*head, ctypes.byref(mp), *tail, _stream(stream)))
@@ -379,12 +381,12 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
 
 def match_noalloc(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
                   precision: int = 0, b_chunks: int = 0, out=None, stream=None,
-                  stats=None) -> List[Dict[str, "object"]]:
+                  stats=None, qblock_waves: int = 0) -> List[Dict[str, "object"]]:
     """match() through lpsift_match_noalloc: the library's fixed per-device
     scratch array is the workspace, so with `out` given nothing is allocated.
     Calls that overlap on one device race on that array."""
     lib = load()
-    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats)
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats, qblock_waves)
     out, head, tail = _match_args(descA, descB, out, None, None, stream)
     _check("lpsift_match_noalloc",
            lib.lpsift_match_noalloc(*head, ctypes.byref(mp), *tail[2:], _stream(stream)))
@@ -466,20 +468,28 @@ def _bucket(n: int) -> int:
 
 def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
                precision: int = 0, candidates: Sequence[int] = TUNE_CANDIDATES, reps: int = 2,
-               cache: Optional[str] = None, stream=None) -> Dict[str, object]:
-    """Pick the fastest candidate-range split (b_chunks) for this set of pairs
-    by timing lpsift_match_tune on the device. cache: optional JSON file; a
-    result is stored under a key of the device name, precision, pair count and
-    power-of-two buckets of the total query and candidate counts, and reused
-    when the key is present. Returns {"b_chunks", "ms", "candidates", "cached"}."""
+               cache: Optional[str] = None, stream=None,
+               waves: Sequence[int] = (0,)) -> Dict[str, object]:
+    """Pick the fastest work split for this set of pairs by timing
+    lpsift_match_tune on the device: the candidate-range split (b_chunks, over
+    `candidates`) and the FP32 contraction's wavefronts per workgroup
+    (qblock_waves, over `waves`; 0 = the default of 4). cache: optional JSON
+    file; a result is stored under a key of the device name, precision, pair
+    count, power-of-two buckets of the total query and candidate counts and the
+    searched values, and reused when the key is present. Returns {"b_chunks",
+    "qblock_waves", "ms" ([len(waves)][len(candidates)]), "candidates", "waves",
+    "cached"}."""
     import json
     import torch
+    cands = [int(c) for c in candidates]
+    wv = [int(w) for w in waves]
     key = None
     if cache is not None:
         nq = sum(int(t.shape[0]) for t in descA)
         nc = sum(int(t.shape[0]) for t in descB)
         key = "|".join(str(v) for v in (torch.cuda.get_device_name(descA[0].device), precision,
-                                        len(descA), _bucket(nq), _bucket(nc)))
+                                        len(descA), _bucket(nq), _bucket(nc),
+                                        ",".join(map(str, cands)), ",".join(map(str, wv))))
         if os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
@@ -493,19 +503,22 @@ def match_tune(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
     def need(nA, nB):
         m = match_params(ratio, abs_thresh, precision, 0, None)
         b = 0
-        for c in candidates:
-            m.b_chunks = int(c)
-            b = max(b, match_workspace_size(nA, nB, m))
+        for w in wv:
+            m.qblock_waves = w
+            for c in cands:
+                m.b_chunks = c
+                b = max(b, match_workspace_size(nA, nB, m))
         return b
     _, head, tail = _match_args(descA, descB, None, None, need, stream)
-    k = len(candidates)
-    ms = (c_f32 * k)()
-    best = c_i32(0)
+    k, nw = len(cands), len(wv)
+    ms = (c_f32 * (k * nw))()
+    best, best_w = c_i32(0), c_i32(0)
     _check("lpsift_match_tune", lib.lpsift_match_tune(
-        *head, ctypes.byref(mp), (c_i32 * k)(*[int(c) for c in candidates]), k, int(reps), *tail,
-        ms, ctypes.byref(best), _stream(stream)))
-    r = {"b_chunks": int(best.value), "ms": [float(v) for v in ms],
-         "candidates": [int(c) for c in candidates], "cached": False}
+        *head, ctypes.byref(mp), (c_i32 * k)(*cands), k, (c_i32 * nw)(*wv), nw, int(reps),
+        *tail, ms, ctypes.byref(best), ctypes.byref(best_w), _stream(stream)))
+    r = {"b_chunks": int(best.value), "qblock_waves": int(best_w.value),
+         "ms": [[float(ms[w * k + c]) for c in range(k)] for w in range(nw)],
+         "candidates": cands, "waves": wv, "cached": False}
     if cache is not None:
         table = {}
         if os.path.exists(cache):

@@ -31,7 +31,7 @@ def pair_list(n: int) -> List[Tuple[int, int]]:
 class AllPairs:
     def __init__(self, images, params: Params, precision: int = 0, b_chunks: int = 0,
                  ratio: float = 0.8, abs_thresh: float = math.inf, ransac_uniforms=None,
-                 ransac_thresh: float = 3.0, u8: bool = False):
+                 ransac_thresh: float = 3.0, u8: bool = False, qblock_waves: int = 0):
         """ransac_uniforms: optional float64 CUDA tensor [n_iter, 4, tries];
         when given, every step ends with the batched GPU RANSAC of all pairs
         (self.ransac: H [pairs, 9], stats [pairs, 3], slot and inlier lists)."""
@@ -42,6 +42,7 @@ class AllPairs:
         self.params = params
         self.precision = precision
         self.b_chunks = b_chunks
+        self.qblock_waves = qblock_waves
         self.ratio = ratio
         self.abs_thresh = abs_thresh
         dev = self.images[0].device
@@ -60,7 +61,7 @@ class AllPairs:
             self.q = [torch.empty((n, DESC_DIM), dtype=torch.uint8, device=dev) for n in self.n_kp]
             need = max(match_u8_workspace_size(self.n_kp[i], self.n_kp[j]) for i, j in self.pairs)
         else:
-            mp = match_params(ratio, abs_thresh, precision, b_chunks, None)
+            mp = match_params(ratio, abs_thresh, precision, b_chunks, None, qblock_waves)
             need = match_workspace_size([self.n_kp[i] for i, _ in self.pairs],
                                         [self.n_kp[j] for _, j in self.pairs], mp)
         self.mws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
@@ -99,7 +100,7 @@ class AllPairs:
             match([self.desc[i] for i, _ in self.pairs], [self.desc[j] for _, j in self.pairs],
                   ratio=self.ratio, abs_thresh=self.abs_thresh, precision=self.precision,
                   b_chunks=self.b_chunks, workspace=self.mws, out=self.out, stream=stream,
-                  stats=self.stats)
+                  stats=self.stats, qblock_waves=self.qblock_waves)
         if self.ransac_uniforms is not None:
             self.ransac = ransac_gpu([self.kps[i] for i, _ in self.pairs],
                                      [self.kps[j] for _, j in self.pairs],

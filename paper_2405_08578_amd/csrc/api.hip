@@ -349,6 +349,9 @@ static int check_match_params(const lpsift_match_params* mp)
     if (!(mp->ratio > 0.0)) return LPSIFT_EINVAL;      // +inf: no ratio test (Eq. 6 alone)
     if (std::isnan(mp->abs_thresh) || !(mp->abs_thresh > 0.0f)) return LPSIFT_EINVAL;
     if (mp->b_chunks < 0 || mp->b_chunks > 16) return LPSIFT_EINVAL;
+    if (mp->qblock_waves != 0 && mp->qblock_waves != 2 && mp->qblock_waves != 4 &&
+        mp->qblock_waves != 8)
+        return LPSIFT_EINVAL;
     if (mp->precision < 0 || mp->precision > 3) return LPSIFT_EINVAL;
     return LPSIFT_OK;
 }
@@ -678,22 +681,28 @@ int lpsift_ransac(const lpsift_keypoints* kpA, const lpsift_keypoints* kpB,
 
 int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float* const* descB,
                       const int64_t* nB, int32_t n_pairs, const lpsift_match_params* mp,
-                      const int32_t* candidates, int32_t n_candidates, int32_t reps,
-                      void* workspace, size_t ws_bytes, int32_t* const* match, float* const* d1,
-                      float* const* d2, float* ms, int32_t* best, void* stream)
+                      const int32_t* candidates, int32_t n_candidates, const int32_t* waves,
+                      int32_t n_waves, int32_t reps, void* workspace, size_t ws_bytes,
+                      int32_t* const* match, float* const* d1, float* const* d2, float* ms,
+                      int32_t* best, int32_t* best_waves, void* stream)
 {
     const int sc = check_match_call(descA, nA, descB, nB, n_pairs, mp, match, d1, d2);
     if (sc != LPSIFT_OK) return sc;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return LPSIFT_EINVAL;
     if (!candidates || n_candidates < 1 || reps < 1 || reps > 1000 || !ms || !best)
         return LPSIFT_EINVAL;
+    if (n_waves < 0 || (n_waves > 0 && (!waves || !best_waves))) return LPSIFT_EINVAL;
+    const int nw = n_waves > 0 ? n_waves : 1;
     lpsift_match_params m = *mp;
-    for (int c = 0; c < n_candidates; ++c) {
-        if (candidates[c] < 1 || candidates[c] > 16) return LPSIFT_EINVAL;
-        m.b_chunks = candidates[c];
-        const size_t need = lpsift_match_workspace_size(nA, nB, n_pairs, &m);
-        if (need == 0) return LPSIFT_EINVAL;
-        if (ws_bytes < need) return LPSIFT_ECAPACITY;
+    for (int w = 0; w < nw; ++w) {
+        if (n_waves > 0) m.qblock_waves = waves[w];
+        for (int c = 0; c < n_candidates; ++c) {
+            if (candidates[c] < 1 || candidates[c] > 16) return LPSIFT_EINVAL;
+            m.b_chunks = candidates[c];
+            const size_t need = lpsift_match_workspace_size(nA, nB, n_pairs, &m);
+            if (need == 0) return LPSIFT_EINVAL;   // also a bad wave count
+            if (ws_bytes < need) return LPSIFT_ECAPACITY;
+        }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
@@ -704,27 +713,34 @@ int lpsift_match_tune(const float* const* descA, const int64_t* nA, const float*
     }
     int st = LPSIFT_OK;
     float best_ms = 0.0f;
-    for (int c = 0; c < n_candidates && st == LPSIFT_OK; ++c) {
-        m.b_chunks = candidates[c];
-        // one untimed run, then reps timed runs
-        st = lpsift_match(descA, nA, descB, nB, n_pairs, &m, workspace, ws_bytes, match, d1, d2,
-                          stream);
-        if (st != LPSIFT_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { st = LPSIFT_EHIP; break; }
-        for (int r = 0; r < reps && st == LPSIFT_OK; ++r)
+    bool first = true;
+    for (int w = 0; w < nw && st == LPSIFT_OK; ++w) {
+        if (n_waves > 0) m.qblock_waves = waves[w];
+        for (int c = 0; c < n_candidates && st == LPSIFT_OK; ++c) {
+            m.b_chunks = candidates[c];
+            // one untimed run, then reps timed runs
             st = lpsift_match(descA, nA, descB, nB, n_pairs, &m, workspace, ws_bytes, match, d1,
                               d2, stream);
-        if (st != LPSIFT_OK) break;
-        float t = 0.0f;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-            st = LPSIFT_EHIP;
-            break;
-        }
-        ms[c] = t / (float)reps;
-        if (c == 0 || ms[c] < best_ms) {
-            best_ms = ms[c];
-            *best = candidates[c];
+            if (st != LPSIFT_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { st = LPSIFT_EHIP; break; }
+            for (int r = 0; r < reps && st == LPSIFT_OK; ++r)
+                st = lpsift_match(descA, nA, descB, nB, n_pairs, &m, workspace, ws_bytes, match,
+                                  d1, d2, stream);
+            if (st != LPSIFT_OK) break;
+            float t = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+                st = LPSIFT_EHIP;
+                break;
+            }
+            const float v = t / (float)reps;
+            ms[w * n_candidates + c] = v;
+            if (first || v < best_ms) {
+                first = false;
+                best_ms = v;
+                *best = candidates[c];
+                if (n_waves > 0) *best_waves = waves[w];
+            }
         }
     }
     // the timing events are released whatever the outcome; a failure to

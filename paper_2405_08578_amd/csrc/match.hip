@@ -61,7 +61,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 
-constexpr int kQB = 256;        // FP32: queries per workgroup
+constexpr int kDefaultWaves = 4; // FP32: wavefronts (64 queries each) per workgroup
 constexpr int kCT = 32;         // FP32: candidates per LDS tile
 constexpr int kRow = 128 + 4;   // FP32: padded LDS row (floats)
 constexpr int kKeep = 4;        // FP32: candidates kept per (query, chunk)
@@ -146,9 +146,11 @@ __device__ inline uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
-// One (query block, chunk) work item of the FP32 contraction. nq: number of
-// queries; qlist (optional) maps list entry i to its query row, results for
-// entry i are stored at position i.
+// One (query block, chunk) work item of the FP32 contraction, kW wavefronts
+// of 64 queries each (a block of 64 kW queries). nq: number of queries;
+// qlist (optional) maps list entry i to its query row, results for entry i
+// are stored at position i.
+template <int kW>
 __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
                                      const int32_t* __restrict__ qlist,
                                      const float* __restrict__ B, int64_t nB,
@@ -161,7 +163,7 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t i0 = qblk * kQB + wave * 64 + col;
+    const int64_t i0 = qblk * (64 * kW) + wave * 64 + col;
     const int64_t i1 = i0 + 32;
     const int64_t q0 = (i0 < nq) ? (qlist ? qlist[i0] : i0) : -1;
     const int64_t q1 = (i1 < nq) ? (qlist ? qlist[i1] : i1) : -1;
@@ -203,23 +205,26 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     int ka1 = 0x7FFFFFFF, ka2 = 0x7FFFFFFF, kb1 = 0x7FFFFFFF, kb2 = 0x7FFFFFFF;
     int ta1 = -1, ta2 = -1, tb1 = -1, tb2 = -1;
 
-    // prefetch: thread t moves float4 number t + 256 k (k < 4) of a 32 x 128
-    // tile (row (t + 256 k) / 32), threads t < 32 also the norm of row t; the
-    // base address is uniform, so a whole tile needs no per-lane address or
-    // bounds arithmetic
-    float4 pf[4];
+    // prefetch: thread t moves float4 number t + nt k (nt = 64 kW threads,
+    // k < kF) of a 32 x 128 tile (row (t + nt k) / 32), threads t < 32 also
+    // the norm of row t; the base address is uniform, so a whole tile needs no
+    // per-lane address or bounds arithmetic
+    constexpr int nt = 64 * kW;
+    constexpr int kF = kCT * 32 / nt;   // float4 per thread per tile
+    static_assert(kF * nt == kCT * 32, "the workgroup moves whole tiles");
+    float4 pf[kF];
     float pn = INFINITY;
     auto fetch = [&](uint32_t t0) {
         const float4* base = reinterpret_cast<const float4*>(B + (int64_t)t0 * 128);
         if (ce - t0 >= (uint32_t)kCT) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) pf[k] = base[tid + 256 * k];
+            for (int k = 0; k < kF; ++k) pf[k] = base[tid + nt * k];
             if (tid < kCT) pn = nrmB[t0 + tid];
         } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                pf[k] = ((uint32_t)((tid + 256 * k) >> 5) < ce - t0) ? base[tid + 256 * k]
-                                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int k = 0; k < kF; ++k)
+                pf[k] = ((uint32_t)((tid + nt * k) >> 5) < ce - t0) ? base[tid + nt * k]
+                                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
             if (tid < kCT) pn = ((uint32_t)tid < ce - t0) ? nrmB[t0 + tid] : INFINITY;
         }
     };
@@ -228,8 +233,8 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     for (uint32_t t0 = cb; t0 < ce; t0 += kCT) {
         __syncthreads();   // the previous tile is no longer read
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int f = tid + 256 * k;
+        for (int k = 0; k < kF; ++k) {
+            const int f = tid + nt * k;
             const int r = f >> 5, c4 = f & 31;
             *reinterpret_cast<float4*>(&tile[r * kRow + c4 * 4]) = pf[k];
         }
@@ -1232,11 +1237,16 @@ __device__ inline int64_t f32_queries(const F32Job& J)
 // (batched pairs with smaller chunks) keep the launch order, which measured
 // faster there.
 constexpr int kXcdRun = 64;
-constexpr int64_t kOneWave = 512;
 
-__global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(const F32Batch b)
+// kW wavefronts per workgroup (2, 4 or 8), 8 / kW workgroups per CU: two
+// waves per SIMD, each with 256 registers.
+template <int kW>
+__global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void match_topk_f32_kernel(const F32Batch b)
 {
-    auto items = [](const F32Job& J) { return (f32_queries(J) + kQB - 1) / kQB * J.chunks; };
+    constexpr int64_t kOneWave = 256 * (8 / kW);   // workgroups resident at once
+    constexpr int64_t qb = 64 * kW;
+    auto items = [](const F32Job& J) { return (f32_queries(J) + qb - 1) / qb * J.chunks; };
     int64_t n_items = 0;
     for (int k = 0; k < b.n; ++k) n_items += items(b.j[k]);
     const bool by_xcd = (gridDim.x % 8u) == 0 && n_items <= kOneWave;
@@ -1252,10 +1262,10 @@ __global__ __launch_bounds__(256, 2) void match_topk_f32_kernel(const F32Batch b
         if (k < 0) return;
         const F32Job& J = b.j[k];
         const int64_t nq = f32_queries(J);
-        const int64_t qblocks = (nq + kQB - 1) / kQB;
+        const int64_t qblocks = (nq + qb - 1) / qb;
         const int chunk = (int)(local / qblocks);
-        topk_f32_item(J.A, nq, J.qlist, J.B, J.nB, J.nrm, J.chunk_len, J.chunks, J.cidx, J.cscore,
-                      local - chunk * qblocks, chunk);
+        topk_f32_item<kW>(J.A, nq, J.qlist, J.B, J.nB, J.nrm, J.chunk_len, J.chunks, J.cidx,
+                          J.cscore, local - chunk * qblocks, chunk);
         __syncthreads();   // the LDS tile is reused by the next item
     }
 }
@@ -1455,18 +1465,20 @@ WsX3 ws_x3(int64_t nA, int64_t nB, const MatchPlan& p, const MatchPlan& pf)
 }
 
 
-MatchPlan plan_chunks(int64_t nA, int64_t nB, int qb_size, int tile, int max_chunks, int req)
+MatchPlan plan_chunks(int64_t nA, int64_t nB, int qb_size, int tile, int max_chunks, int req,
+                      int resident = 512)
 {
     MatchPlan p;
     int chunks = req;
     if (chunks <= 0) {
-        // about two resident workgroups per compute unit (256 CUs): pick the
-        // chunk count whose grid comes closest to a whole number of rounds
+        // `resident` workgroups run at once (two per compute unit for 4-wave
+        // workgroups): pick the chunk count whose grid comes closest to a
+        // whole number of rounds
         const int64_t qblocks = (nA + qb_size - 1) / qb_size;
         chunks = 1;
         double best = -1.0;
         for (int c = 1; c <= max_chunks; ++c) {
-            const double rounds = (double)qblocks * c / 512.0;
+            const double rounds = (double)qblocks * c / (double)resident;
             const double eff = rounds / std::ceil(rounds);
             if (eff > best + 0.02) {   // prefer full rounds, then fewer chunks
                 best = eff;
@@ -1490,16 +1502,33 @@ uint32_t idx_mask_for(int64_t chunk_len)
     return m - 1;
 }
 
-MatchPlan plan_fp32(int64_t nA, int64_t nB, int req)
+// Wavefronts per workgroup of the FP32 contraction (0 = the default).
+int f32_waves(const lpsift_match_params* mp)
 {
-    return plan_chunks(nA, nB, kQB, kCT, 16, req);
+    return mp->qblock_waves > 0 ? mp->qblock_waves : kDefaultWaves;
+}
+
+void launch_f32(int waves, dim3 grid, const F32Batch& b, hipStream_t stream)
+{
+    if (waves == 2)
+        hipLaunchKernelGGL(match_topk_f32_kernel<2>, grid, dim3(128), 0, stream, b);
+    else if (waves == 8)
+        hipLaunchKernelGGL(match_topk_f32_kernel<8>, grid, dim3(512), 0, stream, b);
+    else
+        hipLaunchKernelGGL(match_topk_f32_kernel<4>, grid, dim3(256), 0, stream, b);
+}
+
+// waves: wavefronts per workgroup of the FP32 contraction (2, 4 or 8).
+MatchPlan plan_fp32(int64_t nA, int64_t nB, int req, int waves)
+{
+    return plan_chunks(nA, nB, 64 * waves, kCT, 16, req, 256 * (8 / waves));
 }
 
 // The FP32 re-match of uncertified queries: usually few queries, so the
 // candidate range is split finely (the rescore merges up to 256 entries).
-MatchPlan plan_fallback(int64_t nA, int64_t nB)
+MatchPlan plan_fallback(int64_t nA, int64_t nB, int waves)
 {
-    return plan_chunks(nA, nB, kQB, kCT, 64, 64);
+    return plan_chunks(nA, nB, 64 * waves, kCT, 64, 64, 256 * (8 / waves));
 }
 
 }  // namespace
@@ -1522,7 +1551,7 @@ int launch_quantize_lowp(const float* desc, int64_t n, int precision, void* q, f
 MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp)
 {
     switch (mp->precision) {
-    case 0: return plan_fp32(nA, nB, mp->b_chunks);
+    case 0: return plan_fp32(nA, nB, mp->b_chunks, f32_waves(mp));
     case 3: return plan_chunks(nA, nB, kX3QB, kX3CT, 16, mp->b_chunks);
     default: {
         // the rescore wavefront holds chunks x 2 lane halves x K keys
@@ -1537,11 +1566,11 @@ size_t match_workspace_bytes(int64_t nA, int64_t nB, const lpsift_match_params* 
     const MatchPlan p = plan_match(nA, nB, mp);
     switch (mp->precision) {
     case 0: return ws_f32(nA, nB, p).total;
-    case 3: return ws_x3(nA, nB, p, plan_fallback(nA, nB)).total;
+    case 3: return ws_x3(nA, nB, p, plan_fallback(nA, nB, f32_waves(mp))).total;
     default: {
         // an empty candidate set is handled by the FP32 kernels
         const size_t a = ws_lp(nA, nB, mp->precision, p).total;
-        const size_t b = ws_f32(nA, nB, plan_fp32(nA, nB, 0)).total;
+        const size_t b = ws_f32(nA, nB, plan_fp32(nA, nB, 0, f32_waves(mp))).total;
         return a > b ? a : b;
     }
     }
@@ -1639,7 +1668,7 @@ PairPtrs pair_ptrs(const MatchPairIO& io, const lpsift_match_params* mp)
     char* base = static_cast<char*>(io.ws);
     if (mp->precision == 3) {
         r.p = plan_match(io.nA, io.nB, mp);
-        r.pf = plan_fallback(io.nA, io.nB);
+        r.pf = plan_fallback(io.nA, io.nB, f32_waves(mp));
         const WsX3 L = ws_x3(io.nA, io.nB, r.p, r.pf);
         const WsF32 F = ws_f32(io.nA, io.nB, r.pf);
         char* fbase = base + L.f32;
@@ -1653,7 +1682,7 @@ PairPtrs pair_ptrs(const MatchPairIO& io, const lpsift_match_params* mp)
         r.fidx = reinterpret_cast<int32_t*>(fbase + F.cidx);
         r.fscore = reinterpret_cast<float*>(fbase + F.cscore);
     } else {
-        r.pf = plan_fp32(io.nA, io.nB, mp->precision == 0 ? mp->b_chunks : 0);
+        r.pf = plan_fp32(io.nA, io.nB, mp->precision == 0 ? mp->b_chunks : 0, f32_waves(mp));
         const WsF32 F = ws_f32(io.nA, io.nB, r.pf);
         r.nrm = reinterpret_cast<float*>(base + F.nrm);
         r.fidx = reinterpret_cast<int32_t*>(base + F.cidx);
@@ -1689,6 +1718,8 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
         }
     }
     const bool lp = (mp->precision == 1 || mp->precision == 2);
+    const int waves = f32_waves(mp);
+    const int64_t qb = 64 * waves;   // queries per FP32 workgroup
 
     for (size_t b0 = 0; b0 < act.size(); b0 += kPairs) {
         const size_t b1 = (b0 + kPairs < act.size()) ? b0 + kPairs : act.size();
@@ -1725,7 +1756,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
             if (mp->precision == 0) {
                 main.j[main.n++] = F32Job{P.A, nullptr, nullptr, P.B, O.nrm, Q.fidx, Q.fscore,
                                           P.nA, P.nB, Q.pf.chunk_len, Q.pf.chunks};
-                main_wg += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
+                main_wg += (P.nA + qb - 1) / qb * Q.pf.chunks;
                 rf.j[rf.n++] = RescoreF32Job{P.A, P.B, nullptr, nullptr, Q.fidx, Q.fscore,
                                              P.match, P.d1, P.d2, P.nA, P.nB, Q.pf.chunks};
                 rf_most += (P.nA + 15) / 16;
@@ -1741,7 +1772,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
             rx3_wg += (P.nA + 3) / 4;
             fall.j[fall.n++] = F32Job{P.A, Q.fb, Q.cnt, P.B, O.nrm, Q.fidx, Q.fscore, P.nA, P.nB,
                                       Q.pf.chunk_len, Q.pf.chunks};
-            fall_most += (P.nA + kQB - 1) / kQB * Q.pf.chunks;
+            fall_most += (P.nA + qb - 1) / qb * Q.pf.chunks;
             rf.j[rf.n++] = RescoreF32Job{P.A, P.B, Q.fb, Q.cnt, Q.fidx, Q.fscore, P.match, P.d1,
                                          P.d2, P.nA, P.nB, Q.pf.chunks};
             rf_most += (P.nA + 15) / 16;
@@ -1756,8 +1787,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
         if (main.n > 0) {
             TimedScope ts(LPSIFT_KERNEL_MATCH_FP32, stream);
             // a multiple of 8 workgroups: the XCD-ordered item mapping
-            hipLaunchKernelGGL(match_topk_f32_kernel, dim3((unsigned)((main_wg + 7) / 8 * 8)), dim3(256), 0,
-                               stream, main);
+            launch_f32(waves, dim3((unsigned)((main_wg + 7) / 8 * 8)), main, stream);
         }
         if (x3.n > 0) {
             {
@@ -1771,8 +1801,7 @@ int launch_match_pairs(const MatchPairIO* io, int n, const lpsift_match_params* 
                                    stream, rx3);
             }
             TimedScope ts(LPSIFT_KERNEL_MATCH_REMATCH, stream);
-            hipLaunchKernelGGL(match_topk_f32_kernel, dim3(strided_grid(fall_most, 1024)),
-                               dim3(256), 0, stream, fall);
+            launch_f32(waves, dim3(strided_grid(fall_most, 1024)), fall, stream);
         }
         if (rf.n > 0) {
             TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);

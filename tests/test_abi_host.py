@@ -151,8 +151,12 @@ def test_match_validation_and_workspace(lib):
     for bad in (lp.match_params(ratio=0.0), lp.match_params(ratio=math.nan),
                 lp.match_params(ratio=-math.inf),
                 lp.match_params(abs_thresh=math.nan), lp.match_params(abs_thresh=-1.0),
-                lp.match_params(b_chunks=17), lp.match_params(precision=4)):
+                lp.match_params(b_chunks=17), lp.match_params(precision=4),
+                lp.match_params(qblock_waves=3), lp.match_params(qblock_waves=16),
+                lp.match_params(qblock_waves=-1)):
         assert call(bad) == lp.LPSIFT_EINVAL
+    for w in (2, 4, 8):
+        assert lp.match_workspace_size(nA, nB, lp.match_params(qblock_waves=w)) > 0
     # low-precision paths need more workspace (quantised copies, keys, FP32 fallback)
     for prec in (1, 2, 3):
         mlp = lp.match_params(precision=prec)
@@ -195,15 +199,20 @@ def test_match_tune_validation(lib):
         m = lp.match_params(b_chunks=c)
         needs.append(lp.match_workspace_size(nA, nB, m))
     assert needs[1] > needs[0]             # more chunks keep more candidates per query
-    ms = (ctypes.c_float * 4)()
+    ms = (ctypes.c_float * 16)()
     best = ctypes.c_int32(0)
+    best_w = ctypes.c_int32(0)
 
-    def call(cands, reps=2, wsb=max(needs), m=mp, msp=ms, bp=ctypes.byref(best), dA=FAKE):
+    def call(cands, reps=2, wsb=max(needs), m=mp, msp=ms, bp=ctypes.byref(best), dA=FAKE,
+             waves=(), wp=ctypes.byref(best_w)):
         k = len(cands)
+        nw = len(waves) if waves is not None else 1
+        wa = (ctypes.c_int32 * max(nw, 1))(*waves) if waves is not None else None
         return lib.lpsift_match_tune(arr(dA, FAKE), i64(*nA), arr(FAKE, FAKE), i64(*nB), 2,
                                      ctypes.byref(m), (ctypes.c_int32 * max(k, 1))(*cands), k,
-                                     reps, 0x100000, wsb, arr(FAKE, FAKE), arr(FAKE, FAKE),
-                                     arr(FAKE, FAKE), msp, bp, None)
+                                     wa, nw, reps, 0x100000, wsb,
+                                     arr(FAKE, FAKE), arr(FAKE, FAKE), arr(FAKE, FAKE), msp, bp,
+                                     wp, None)
     assert call([1, 16], wsb=needs[1] - 1) == lp.LPSIFT_ECAPACITY   # the largest must fit
     assert call([0, 4]) == lp.LPSIFT_EINVAL
     assert call([17]) == lp.LPSIFT_EINVAL
@@ -213,6 +222,12 @@ def test_match_tune_validation(lib):
     assert call([2], bp=None) == lp.LPSIFT_EINVAL
     assert call([2], dA=FAKE + 4) == lp.LPSIFT_EINVAL
     assert call([2], m=lp.match_params(ratio=-1.0)) == lp.LPSIFT_EINVAL
+    # the wave-count dimension: each value 0, 2, 4 or 8, arrays given when used
+    assert call([2], waves=(3,)) == lp.LPSIFT_EINVAL
+    assert call([2], waves=(2, 16)) == lp.LPSIFT_EINVAL
+    assert call([2], waves=None) == lp.LPSIFT_EINVAL            # n_waves 1, no array
+    assert call([2], waves=(2, 4), wp=None) == lp.LPSIFT_EINVAL
+    assert call([2], m=lp.match_params(qblock_waves=5)) == lp.LPSIFT_EINVAL
 
 
 def test_tune_bucket():

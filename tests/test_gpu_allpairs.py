@@ -124,14 +124,16 @@ def test_allpairs_tune_small(gpu, tmp_path):
     B = [ap.desc[j] for _, j in ap.pairs]
     cache = str(tmp_path / "tune.json")
     say("match tune")
-    r = lp.match_tune(A, B, candidates=(1, 2, 4), reps=1, cache=cache)
-    assert r["b_chunks"] in (1, 2, 4) and len(r["ms"]) == 3 and not r["cached"]
-    assert all(m > 0 for m in r["ms"])
-    assert r["ms"][r["candidates"].index(r["b_chunks"])] == min(r["ms"])
-    r2 = lp.match_tune(A, B, candidates=(1, 2, 4), reps=1, cache=cache)
-    assert r2["cached"] and r2["b_chunks"] == r["b_chunks"]
+    r = lp.match_tune(A, B, candidates=(1, 2, 4), waves=(2, 4, 8), reps=1, cache=cache)
+    assert r["b_chunks"] in (1, 2, 4) and r["qblock_waves"] in (2, 4, 8) and not r["cached"]
+    assert len(r["ms"]) == 3 and all(len(row) == 3 for row in r["ms"])
+    assert all(m > 0 for row in r["ms"] for m in row)
+    best = r["ms"][r["waves"].index(r["qblock_waves"])][r["candidates"].index(r["b_chunks"])]
+    assert best == min(m for row in r["ms"] for m in row)
+    r2 = lp.match_tune(A, B, candidates=(1, 2, 4), waves=(2, 4, 8), reps=1, cache=cache)
+    assert r2["cached"] and (r2["b_chunks"], r2["qblock_waves"]) == (r["b_chunks"], r["qblock_waves"])
     # the tuned split gives lists that pass the oracle rule
-    out = lp.match(A, B, b_chunks=r["b_chunks"])
+    out = lp.match(A, B, b_chunks=r["b_chunks"], qblock_waves=r["qblock_waves"])
     i, j = ap.pairs[0]
     check_rule_i(ap.desc[i].cpu().numpy(), ap.desc[j].cpu().numpy(),
                  {k: v.cpu().numpy() for k, v in out[0].items()})

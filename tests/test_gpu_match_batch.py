@@ -78,3 +78,25 @@ def test_batch_shared_sets_chunks(gpu, chunks):
         for k in a:
             assert np.array_equal(a[k], b[k]), (i, j, k)
     check_rule_i(sets[2].cpu().numpy(), sets[1].cpu().numpy(), host(res[1]))
+
+
+@pytest.mark.parametrize("precision", [0, 3])
+def test_wave_counts_give_identical_lists(gpu, precision):
+    """The FP32 contraction's workgroup shape (2, 4 or 8 wavefronts of 64
+    queries) changes only the work split: lists, d1 and d2 equal bit for bit
+    (the split path's FP32 re-match uses the same shape)."""
+    import torch
+    sets = [torch.from_numpy(s).to(gpu) for s in descriptor_sets([900, 1300, 513, 77], 91)]
+    pairs = [(0, 1), (2, 1), (3, 0), (1, 3)]
+    A = [sets[i] for i, _ in pairs]
+    B = [sets[j] for _, j in pairs]
+    for chunks in (0, 3):
+        say("batched match, wave counts", precision, chunks)
+        ref = [host(r) for r in lp.match(A, B, precision=precision, b_chunks=chunks, qblock_waves=4)]
+        for w in (2, 8):
+            got = [host(r) for r in lp.match(A, B, precision=precision, b_chunks=chunks,
+                                             qblock_waves=w)]
+            for a, b in zip(ref, got):
+                for k in a:
+                    assert np.array_equal(a[k], b[k]), (w, chunks, k)
+    check_rule_i(sets[2].cpu().numpy(), sets[1].cpu().numpy(), ref[1])
