@@ -433,8 +433,14 @@ def precision_variants(args, dev, tiles, imgs, P, n_kp, flops, tune, ref_lists, 
     sampled = {"fp32": [ref_lists[k] for k in sidx]}
     variants = {}
     peaks = {3: PEAK_BF16_MFMA, 1: PEAK_BF16_MFMA, 2: PEAK_FP8_MFMA}
+    # the quantised matchers' candidate split, tuned like the FP32 one
+    A = [ap_desc[i] for i, _ in ap_pairs]
+    B = [ap_desc[j] for _, j in ap_pairs]
+    lp_tune = {prec: lp.match_tune(A, B, precision=prec, candidates=TUNE_CHUNKS, reps=1)
+               for prec in (1, 2)}
+    del A, B
     for prec, name in ((3, "split_bf16x3_certified"), (1, "bf16"), (2, "fp8")):
-        bc = tune["split"]["b_chunks"] if prec == 3 else 0
+        bc = tune["split"]["b_chunks"] if prec == 3 else lp_tune[prec]["b_chunks"]
         qw = tune["split"]["qblock_waves"] if prec == 3 else 0
         ap = AllPairs(imgs, P, precision=prec, b_chunks=bc, qblock_waves=qw)
         ap.capture()
@@ -450,7 +456,7 @@ def precision_variants(args, dev, tiles, imgs, P, n_kp, flops, tune, ref_lists, 
         same = sum(int((a["match"] == b["match"]).sum()) for a, b in zip(lists, ref_lists))
         key = "match_split" if prec == 3 else "match_lowp"
         v = {"ms_per_step_graph": round(wall, 3), "pairs_per_s": round(36 * 1000.0 / wall, 3),
-             "kernels": kt,
+             "b_chunks": bc, "kernels": kt,
              "list_agreement_with_fp32": round(same / sum(len(m["match"]) for m in lists), 6)}
         if key in kt:
             tf = flops / (kt[key]["ms_per_step"] * 1e-3) / 1e12

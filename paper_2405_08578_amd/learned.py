@@ -381,4 +381,4 @@ def load_weights(path: str, device=None):
     return (t.to(device) if device is not None else t), info
 
 
-DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "scorer", "lpsift_scorer_v1")
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "scorer", "lpsift_scorer_v2")

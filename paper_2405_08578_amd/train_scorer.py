@@ -1,7 +1,7 @@
 """Train the learned keypoint scorer on seeded synthetic pairs.
 
-    python -m paper_2405_08578_amd.train_scorer --pairs 500 --steps 12000 \
-        --out paper_2405_08578_amd/scorer/lpsift_scorer_v1
+    python -m paper_2405_08578_amd.train_scorer --pairs 500 --steps 24000 \
+        --out paper_2405_08578_amd/scorer/lpsift_scorer_v2
 
 Pairs are generated like the 2600x1600 benchmark pair (instances 100 ..
 100 + pairs - 1 of that configuration, disjoint from the benchmark's instance
@@ -111,7 +111,7 @@ def main(argv=None):
             "steps": args.steps, "batch": args.batch, "lr": args.lr,
             "lr_final": args.lr_final, "neg_per_pos": args.neg_per_pos, "seed": args.seed,
             "loss_history": losses,
-            "ransac_iters": L.RANSAC_ITERS,
+            "ransac_iters": L.RANSAC_ITERS, "ransac_refine_rounds": L.REFINE_ROUNDS,
             "heldout": [dict(zip(("instance", "ransac_plain", "ransac_learned", "gt_plain",
                                   "gt_learned", "plain_inliers_kept"), e)) for e in ev],
             "heldout_inlier_retention": (kept_all / tot_p) if tot_p else None,
