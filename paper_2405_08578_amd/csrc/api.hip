@@ -53,6 +53,21 @@ int make_geometry(const lpsift_params* p, Geometry* g)
         G.n_desc = disc_count(G.r2_desc);
         G.n_buckets = G.n_desc <= kBucketMaxEntries ? kDescBuckets : 1;
         G.cap_desc = G.n_desc;
+        // Descriptor votes are 32-bit fixed point. A bin takes from every
+        // pixel of its cell's support (a square of side 2 w_s) at most
+        // 362 (> 255 sqrt 2, the largest gradient) times the bilinear cell
+        // weight (the Gaussian and direction weights are <= 1); over the
+        // integer pixels the bilinear weights of one cell sum to less than
+        // w_s^2 + 4.5 w_s + 1 at any angle and position (the weight is
+        // log-concave, so each row and then the rows sum to at most their
+        // integral plus their largest term: w_s^2 + 3 sqrt 2 w_s + 1). Rounding adds at most 1/2 per
+        // vote, one vote per support pixel, < (2 sqrt 2 w_s + 2)^2 of them.
+        // The scale keeps the bound below 0.98 of 2^32.
+        const double cell_sum = ws * ws + 4.5 * ws + 1.0;
+        const double n_votes = (2.0 * std::sqrt(2.0) * ws + 2.0) * (2.0 * std::sqrt(2.0) * ws + 2.0);
+        const double dscale = (0.98 * 4294967296.0 - 0.5 * n_votes) / (362.0 * cell_sum);
+        G.dscale = (float)dscale;
+        G.dinv = (float)(1.0 / (double)G.dscale);
         entries += G.n_buckets * G.cap_desc;
     }
     g->table_entries = entries;

@@ -18,13 +18,17 @@
 //     consecutive table entries and mostly neighbouring pixels of the field;
 //     lanes of even and odd index vote into two copies of the histogram, which
 //     halves the collisions of neighbouring pixels on one bin. Votes are
-//     accumulated in LDS as 64-bit fixed point with integer atomics:
-//     ds_add_u64 runs at close to full rate where ds_add_f32 does not, and
-//     integer sums do not depend on the order of the votes, so the result is
-//     bit-identical from run to run. A single vote is at most 255 sqrt 2 < 362
-//     (all interpolation weights <= 1), so at the fixed scale 2^23 it fits 32
-//     bits and converts with one v_cvt_u32_f32 (truncation, a quantum of
-//     2^-23 per vote); the 64-bit bins cannot overflow below 2^41 votes.
+//     accumulated in LDS as fixed point with integer atomics: ds_add_u64
+//     runs at close to full rate where ds_add_f32 does not, and integer sums
+//     do not depend on the order of the votes, so the result is bit-identical
+//     from run to run. Orientation votes (at most 255 sqrt 2 < 362, all
+//     weights <= 1) are scaled by 2^23, truncated to 32 bits by one
+//     v_cvt_u32_f32 and added to 64-bit bins. Descriptor votes are scaled per
+//     scale so that no bin can reach 2^32 (the bound is derived with the
+//     geometry) and rounded to nearest; a descriptor visit's two direction
+//     bins o and o + 1 (mod 8) of a cell then go out as one 64-bit atomic,
+//     the low word to bin o and the high word to bin o + 1 (no carry crosses
+//     the words), which halves the LDS atomics of the descriptor.
 //     Orientation (36 bins, smoothing, argmax,
 //     parabola), then the 128-bin descriptor, normalisation, clipping at 0.2
 //     and renormalisation happen in the same wave; the descriptor row is
@@ -54,6 +58,7 @@ struct TableArgs {
     int32_t cap_desc[LPSIFT_MAX_SCALES];
     int32_t n_buckets[LPSIFT_MAX_SCALES];
     float k_desc[LPSIFT_MAX_SCALES];
+    float dscale[LPSIFT_MAX_SCALES];       // descriptor vote scale (folded into the weights)
     double inv_ws[LPSIFT_MAX_SCALES];
 };
 
@@ -63,13 +68,13 @@ __device__ inline int32_t pack_offset(int dx, int dy)
 }
 
 // One disc entry: the offset as floats (for the rotation), its Gaussian
-// weight exp2((dx^2 + dy^2) k) (computed once here, with the same product and
-// v_exp_f32 a visit would use), and the packed integer offset (for the field
-// address) -- one 16-byte load per visit.
-__device__ inline float4 disc_entry(int dx, int dy, float k)
+// weight exp2((dx^2 + dy^2) k) times the votes' fixed-point scale (computed
+// once here), and the packed integer offset (for the field address) -- one
+// 16-byte load per visit.
+__device__ inline float4 disc_entry(int dx, int dy, float k, float scale)
 {
     return make_float4((float)dx, (float)dy,
-                       __builtin_amdgcn_exp2f((float)(dx * dx + dy * dy) * k),
+                       __builtin_amdgcn_exp2f((float)(dx * dx + dy * dy) * k) * scale,
                        __int_as_float(pack_offset(dx, dy)));
 }
 
@@ -188,10 +193,11 @@ __device__ void build_table(const TableArgs& a, float4* tables, int32_t* counts,
     float4* out = tables + (orient ? (int64_t)a.off_orient[s]
                                    : (int64_t)a.off_desc[s] + (int64_t)b * a.cap_desc[s]);
     const float k = orient ? a.k_orient[s] : a.k_desc[s];
+    const float vscale = orient ? kOrientVoteScale : a.dscale[s];
     {
         int dx = dx_first, dy = dy_first, hw = hw_first;
         for (int e = 0; e < j1 - j0; ++e) {
-            if (!filter || ((keep >> e) & 1u)) out[at++] = disc_entry(dx, dy, k);
+            if (!filter || ((keep >> e) & 1u)) out[at++] = disc_entry(dx, dy, k, vscale);
             if (++dx > hw) {
                 ++dy;
                 hw = isqrt_floor(r2 - dy * dy);
@@ -336,13 +342,31 @@ __device__ inline float wave_sum(float v)
     return v;
 }
 
-// Fixed-point scale of the votes (see the header); votes arrive pre-scaled.
-constexpr float kVoteScale = 8388608.0f;           // 2^23
-constexpr float kVoteInv = 1.0f / 8388608.0f;
+constexpr float kOrientVoteInv = 1.0f / kOrientVoteScale;
 
+// Orientation vote, pre-scaled: truncated to an integer, added to a 64-bit bin.
 __device__ inline void vote(unsigned long long* h, float w_scaled)
 {
     atomicAdd(h, (unsigned long long)(uint32_t)w_scaled);
+}
+
+// floor(x) as an integer in one instruction (|x| well inside the int range).
+__device__ inline int floor_int(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Descriptor bin b (cell b / 8, direction b % 8) of one histogram copy: the
+// votes of visits whose lower direction bin is o sit in 64-bit word
+// (cell, o), for bin o in its low and for bin o + 1 (mod 8) in its high
+// 32-bit word.
+__device__ inline unsigned long long desc_bin(const unsigned long long* h, int b)
+{
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(h);
+    const int prev = (b & ~7) | ((b + 7) & 7);
+    return (unsigned long long)w[2 * b] + (unsigned long long)w[2 * prev + 1];
 }
 
 // Makes a wave's LDS writes visible to its own later reads. Enough where each
@@ -428,9 +452,10 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ft[u].x == 0.0f) continue;
-            // Gaussian weight from the table (its exponent is above -7 for
-            // every geometry, far from the denormal range: v_exp_f32 alone)
-            const float wt = ft[u].x * kVoteScale * gw[u];
+            // Gaussian weight times 2^23 from the table (its exponent is above
+            // -7 for every geometry, far from the denormal range: v_exp_f32
+            // alone)
+            const float wt = ft[u].x * gw[u];
             const float t = ft[u].y * 36.0f;
             const float k0f = floorf(t);
             const float fr = t - k0f;
@@ -450,7 +475,7 @@ __device__ __forceinline__ float orient_hist(unsigned long long* ho, int lane, b
 {
     orient_votes<64, kC>(ho, lane, live, kx, ky, field, W, H, G, tables);
     wave_sync();
-    const float inv = kVoteInv;
+    const float inv = kOrientVoteInv;
     // lane k < 36 converts bin k once; its neighbours come by shuffles
     float h0 = 0.0f;
     if (lane < 36) {
@@ -491,7 +516,8 @@ __device__ inline float peak_turns(float sm, int k, float h0)
 // normalise, clip at 0.2, renormalise; lane l returns elements l and l + 64.
 // kWaveOnly: the wave synchronises alone (the caller's waves may diverge).
 // Descriptor votes of one keypoint at angle th_turns into hist[0..128) of
-// each histogram copy; lanes as in orient_votes.
+// each histogram copy (the packed layout read by desc_bin); lanes as in
+// orient_votes.
 template <int kStride, int kC = kCopies>
 __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bool live, int kx,
                                            int ky, const float2* field, int W, int H,
@@ -502,6 +528,7 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
     sn = __builtin_amdgcn_sinf(th_turns);   // v_sin_f32 / v_cos_f32 take revolutions
     cs = __builtin_amdgcn_cosf(th_turns);
     const float ca = cs * G.inv_ws, sa = sn * G.inv_ws;   // rotation by -theta, in cells
+    const float th8 = th_turns * 8.0f;
     // the bucket of theta (any angle, wrapped to [0, 1) turns by the mask)
     const int bk = G.n_buckets > 1 ? ((int)floorf(th_turns * (float)kDescBuckets) & (kDescBuckets - 1)) : 0;
     const int nd = live ? bcount[bk] : 0;
@@ -515,9 +542,12 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
         float fdx[kUnroll], fdy[kUnroll], gw[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
+            // loads without branches: a lane past the list reads entry 0, and
+            // its visit, like one outside the image, reads field pixel 0 (a
+            // border pixel, so of magnitude 0: it casts no vote)
             const int j = (it0 + u) * kStride + sub;
-            ok[u] = (it0 + u < perd) && j < nd;
-            const float4 e = ok[u] ? tabd[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            ok[u] = j < nd;
+            const float4 e = tabd[ok[u] ? (uint32_t)j : 0u];
             const int32_t pk = __float_as_int(e.w);
             dx[u] = (int)(int16_t)(pk & 0xFFFF);
             dy[u] = pk >> 16;
@@ -528,30 +558,30 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int px = kx + dx[u], py = ky + dy[u];
-            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
-            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
+            const bool in = ok[u] & ((unsigned)px < (unsigned)W) & ((unsigned)py < (unsigned)H);
+            const uint32_t at = (uint32_t)(py * W + px);
+            ft[u] = field[in ? at : 0u];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ft[u].x == 0.0f) continue;
-            // offset rotated by -theta, in subregion units
-            const float uu = fmaf(ca, fdx[u], sa * fdy[u]);
-            const float vv = fmaf(ca, fdy[u], -(sa * fdx[u]));
-            if (fabsf(uu) >= 2.5f || fabsf(vv) >= 2.5f) continue;   // no cell reachable
-            const float m = ft[u].x * kVoteScale * gw[u];
+            // offset rotated by -theta, in subregion units, shifted by 1.5 so
+            // that cell i covers [i, i + 1); offsets outside the square of
+            // reachable cells find no cell in range below
+            const float cu = fmaf(ca, fdx[u], fmaf(sa, fdy[u], 1.5f));
+            const float cv = fmaf(ca, fdy[u], fmaf(-sa, fdx[u], 1.5f));
+            // Gaussian weight and vote scale from the table
+            const float m = ft[u].x * gw[u];
             // direction bins o0 and o0 + 1 (mod 8) of the angle relative to theta
-            const float t = __builtin_amdgcn_fractf(ft[u].y - th_turns) * 8.0f;   // [0, 8)
-            const int o0 = (int)t;
-            const float fo = t - (float)o0;
-            const int o1 = (o0 + 1) & 7;
-            const float m0 = m * (1.0f - fo), m1 = m * fo;
-            const float cu = uu + 1.5f, cv = vv + 1.5f;
-            const float ix0f = floorf(cu), iy0f = floorf(cv);
-            const float fx = cu - ix0f, fy = cv - iy0f;
-            const int ix0 = (int)ix0f, iy0 = (int)iy0f;   // -1 .. 3
-            // bins o0 and o1 of the four cells at constant offsets from two bases
+            const float t = fmaf(ft[u].y, 8.0f, -th8);   // (-8, 8)
+            const int o0 = floor_int(t) & 7;
+            const float fo = __builtin_amdgcn_fractf(t);
+            const float m1 = m * fo;
+            const float m0 = fmaf(ft[u].x, gw[u], -m1);   // explicit: the same rounding in every kernel
+            const int ix0 = floor_int(cu), iy0 = floor_int(cv);
+            const float fx = __builtin_amdgcn_fractf(cu), fy = __builtin_amdgcn_fractf(cv);
+            // word (cell, o0) of the four cells at constant offsets from one base
             unsigned long long* b0 = hv + (iy0 * 4 + ix0) * 8 + o0;
-            unsigned long long* b1 = hv + (iy0 * 4 + ix0) * 8 + o1;
 #pragma unroll
             for (int jy = 0; jy < 2; ++jy) {
                 if ((unsigned)(iy0 + jy) > 3u) continue;
@@ -560,8 +590,10 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
                 for (int jx = 0; jx < 2; ++jx) {
                     if ((unsigned)(ix0 + jx) > 3u) continue;
                     const float wxy = (jx ? fx : 1.0f - fx) * wy;
-                    vote(b0 + (jy * 4 + jx) * 8, m0 * wxy);
-                    vote(b1 + (jy * 4 + jx) * 8, m1 * wxy);
+                    // round to nearest: non-negative values, + 1/2, truncate
+                    const uint32_t lo = (uint32_t)fmaf(m0, wxy, 0.5f);
+                    const uint32_t hi = (uint32_t)fmaf(m1, wxy, 0.5f);
+                    atomicAdd(b0 + (jy * 4 + jx) * 8, ((unsigned long long)hi << 32) | lo);
                 }
             }
         }
@@ -577,12 +609,12 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 {
     desc_votes<64, kC>(hist, lane, live, kx, ky, field, W, H, G, tables, bcount, th_turns);
     hist_sync<kWaveOnly>();
-    const float dinv = kVoteInv;
+    const float dinv = G.dinv;
     unsigned long long s0 = 0ull, s1 = 0ull;
 #pragma unroll
     for (int c = 0; c < kC; ++c) {
-        s0 += hist[c * kBins + lane];
-        s1 += hist[c * kBins + lane + 64];
+        s0 += desc_bin(hist + c * kBins, lane);
+        s1 += desc_bin(hist + c * kBins, lane + 64);
     }
     float d0 = (float)s0 * dinv, d1 = (float)s1 * dinv;
     float inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(fmaf(d0, d0, d1 * d1))), 1e-12f));
@@ -796,7 +828,7 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
         unsigned long long v = 0ull;
 #pragma unroll
         for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kBins + 128 + k];
-        return (float)v * kVoteInv;
+        return (float)v * kOrientVoteInv;
     };
     // each bin converted once: lane sub holds bin sub (ha) and, for sub < 4,
     // bin 32 + sub (hb); a neighbour bin comes from the lane that holds it
@@ -849,8 +881,8 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     for (int q = 0; q < 4; ++q) {
         unsigned long long v = 0ull;
 #pragma unroll
-        for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kBins + sub + 32 * q];
-        d[q] = (float)v * kVoteInv;
+        for (int c = 0; c < kHalfCopies; ++c) v += desc_bin(hist + c * kBins, sub + 32 * q);
+        d[q] = (float)v * G.dinv;
     }
     auto half_norm = [&]() {
         float ss = fmaf(d[0], d[0], d[2] * d[2]) + fmaf(d[1], d[1], d[3] * d[3]);
@@ -994,6 +1026,7 @@ int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, c
         ta.cap_desc[s] = G.cap_desc;
         ta.n_buckets[s] = G.n_buckets;
         ta.k_desc[s] = G.k_desc;
+        ta.dscale[s] = G.dscale;
         ta.inv_ws[s] = 1.0 / (double)G.ws;
     }
     // the tables are built by the first field launch (n_table workgroups)

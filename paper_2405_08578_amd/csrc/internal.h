@@ -50,7 +50,12 @@ struct ScaleGeom {
     int n_desc;        // entries of the whole descriptor disc
     int n_buckets;     // orientation buckets of the descriptor table: kDescBuckets or 1
     int cap_desc;      // entries reserved per bucket (n_desc)
+    float dscale;      // fixed-point scale of the descriptor votes (a bin stays below 2^32)
+    float dinv;        // 1 / dscale
 };
+
+// Fixed-point scale of the orientation votes (64-bit bins).
+constexpr float kOrientVoteScale = 8388608.0f;   // 2^23
 
 // The descriptor disc is stored once per orientation bucket, keeping only the
 // entries that the square of reachable subregions can cover for some angle of

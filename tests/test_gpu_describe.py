@@ -98,6 +98,26 @@ def test_describe_properties_and_determinism(gpu):
     assert a.min() >= 0
 
 
+@pytest.mark.parametrize("kind", ["binary_noise", "binary_blocks"])
+def test_describe_high_contrast(gpu, kind):
+    # gradients near the largest possible (255 per step) in every support:
+    # the fixed-point descriptor bins, scaled so that no bin can reach 2^32,
+    # must still give the oracle's descriptors
+    rng = np.random.default_rng(7)
+    h, w = 257, 300
+    if kind == "binary_noise":
+        img = (rng.integers(0, 2, (h, w)) * 255).astype(np.uint8)
+    else:
+        blocks = rng.integers(0, 2, (h // 3 + 1, w // 3 + 1)) * 255
+        img = np.repeat(np.repeat(blocks, 3, 0), 3, 1)[:h, :w].astype(np.uint8)
+    Ls = [16, 32, 64, 128]
+    say("describe high contrast", kind, h, w)
+    P = lp.Params(Ls)
+    kps, th, de = lp.features([to_dev(img, gpu)], P)
+    kpn = kp_numpy(kps[0])
+    check(img, kpn, th[0].cpu().numpy(), de[0].cpu().numpy(), Ls, max_ambiguous=0.05)
+
+
 def test_describe_flat_image(gpu):
     img = np.full((64, 80), 200, np.uint8)
     P = lp.Params([16, 32])

@@ -4,8 +4,9 @@ disc once per orientation bucket, keeping every entry that the square of
 reachable subregions (|u|, |v| < 2.5 subregions after rotating the offset by
 -theta, Sec. 2.3) can cover for an angle of the bucket.
 
-Layout (16-byte entries: dx, dy as floats, the Gaussian weight, the offset
-packed as two int16): per scale the orientation disc, then 64 bucket lists of
+Layout (16-byte entries: dx, dy as floats, the Gaussian weight times the
+votes' fixed-point scale, the offset packed as two int16): per scale the
+orientation disc, then 64 bucket lists of
 n_desc entries each (one whole list when the disc has more than 8,192
 entries); then the int32 entry counts [8 scales][64 buckets]. The geometry is
 recomputed here from Eq. 3-4 as the library derives it."""
@@ -44,6 +45,11 @@ def geometry(Ls, d=4):
              "ko": np.float32(-log2e / (2.0 * (0.5 * ws) ** 2)),
              "kd": np.float32(-log2e / (2.0 * (0.5 * d) ** 2 * ws * ws))}
         g["no"], g["nd"] = len(disc(g["r2o"])), len(disc(g["r2d"]))
+        # descriptor vote scale: 362 (> the largest gradient, 255 sqrt 2) times
+        # a bound on one cell's bilinear weights over the pixels, plus 1/2 per
+        # vote, stays below 0.98 of 2^32
+        nv = (2.0 * math.sqrt(2.0) * ws + 2.0) ** 2
+        g["dscale"] = float(np.float32((0.98 * 2.0 ** 32 - 0.5 * nv) / (362.0 * (ws * ws + 4.5 * ws + 1.0))))
         g["nb"] = BUCKETS if g["nd"] <= 8192 else 1
         g["off_o"] = entries
         entries += g["no"]
@@ -80,12 +86,12 @@ def check_tables(raw, Ls):
     coff = (n_entries * 16 + 255) // 256 * 256
     counts = raw[coff:coff + 8 * BUCKETS * 4].view(np.int32).reshape(8, BUCKETS)
     for s, g in enumerate(scales):
-        # orientation disc: whole, row-major, weights exp2(r^2 k)
+        # orientation disc: whole, row-major, weights exp2(r^2 k) 2^23
         e, dx, dy = entries_of(tab, g["off_o"], g["no"])
         assert list(zip(dx.tolist(), dy.tolist())) == disc(g["r2o"])
         assert np.array_equal(e[:, 0], dx.astype(np.float32))
         assert np.array_equal(e[:, 1], dy.astype(np.float32))
-        w = np.exp2((dx * dx + dy * dy).astype(np.float64) * float(g["ko"]))
+        w = np.exp2((dx * dx + dy * dy).astype(np.float64) * float(g["ko"])) * 2.0 ** 23
         assert np.allclose(e[:, 2], w, rtol=2e-6, atol=0)
         D = np.array(disc(g["r2d"]))
         inv = float(np.float32(1.0 / np.float32(g["ws"])))
@@ -95,8 +101,8 @@ def check_tables(raw, Ls):
             got = list(zip(dx.tolist(), dy.tolist()))
             assert got == sorted(got, key=lambda t: (t[1], t[0])), "row-major order"
             assert len(set(got)) == n
-            w = np.exp2((dx * dx + dy * dy).astype(np.float64) * float(g["kd"]))
-            assert np.allclose(e[:, 2], w, rtol=2e-6, atol=0)
+            w = np.exp2((dx * dx + dy * dy).astype(np.float64) * float(g["kd"])) * g["dscale"]
+            assert np.allclose(e[:, 2], w, rtol=3e-6, atol=0)
             if g["nb"] == 1:
                 assert got == [tuple(t) for t in D.tolist()]
                 continue
