@@ -313,7 +313,7 @@ constexpr int kWaves = 4;          // keypoints per workgroup
 constexpr int kUnroll = 4;         // visits per lane per step
 constexpr int kBins = 128 + 36;    // descriptor bins, then orientation bins
 // Bins before the first histogram of a workgroup's LDS: a descriptor vote
-// addresses its four cells from one base at cell (iy0, ix0) >= (-1, -1),
+// addresses its four cells from one base at a cell index clamped to >= -5,
 // which may lie up to 5 cells before the histogram (only in-range cells are
 // written).
 constexpr int kCellPad = 40;
@@ -435,9 +435,10 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
         float gw[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
+            // branch-free loads, as in desc_votes
             const int j = (it0 + u) * kStride + sub;
-            ok[u] = (it0 + u < per) && j < n;
-            const float4 e = ok[u] ? tab[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            ok[u] = j < n;
+            const float4 e = tab[ok[u] ? (uint32_t)j : 0u];
             const int32_t pk = __float_as_int(e.w);
             dx[u] = (int)(int16_t)(pk & 0xFFFF);
             dy[u] = pk >> 16;
@@ -446,8 +447,9 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int px = kx + dx[u], py = ky + dy[u];
-            ok[u] = ok[u] && px >= 0 && px < W && py >= 0 && py < H;
-            ft[u] = ok[u] ? field[py * W + px] : make_float2(0.0f, 0.0f);
+            const bool in = ok[u] & ((unsigned)px < (unsigned)W) & ((unsigned)py < (unsigned)H);
+            const uint32_t at = (uint32_t)(__mul24(py, W) + px);
+            ft[u] = field[in ? at : 0u];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -456,10 +458,11 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
             // -7 for every geometry, far from the denormal range: v_exp_f32
             // alone)
             const float wt = ft[u].x * gw[u];
+            // the product is rounded before fract and floor take it (neither
+            // can fuse with it), so every kernel gets the same bins
             const float t = ft[u].y * 36.0f;
-            const float k0f = floorf(t);
-            const float fr = t - k0f;
-            int k0 = (int)k0f;
+            const float fr = __builtin_amdgcn_fractf(t);
+            int k0 = floor_int(t);
             if (k0 >= 36) k0 -= 36;
             const int k1 = (k0 == 35) ? 0 : k0 + 1;
             vote(hv + k0, (1.0f - fr) * wt);
@@ -559,7 +562,7 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
         for (int u = 0; u < kUnroll; ++u) {
             const int px = kx + dx[u], py = ky + dy[u];
             const bool in = ok[u] & ((unsigned)px < (unsigned)W) & ((unsigned)py < (unsigned)H);
-            const uint32_t at = (uint32_t)(py * W + px);
+            const uint32_t at = (uint32_t)(__mul24(py, W) + px);   // 24-bit multiply: full rate
             ft[u] = field[in ? at : 0u];
         }
 #pragma unroll
@@ -580,8 +583,11 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
             const float m0 = fmaf(ft[u].x, gw[u], -m1);   // explicit: the same rounding in every kernel
             const int ix0 = floor_int(cu), iy0 = floor_int(cv);
             const float fx = __builtin_amdgcn_fractf(cu), fy = __builtin_amdgcn_fractf(cv);
-            // word (cell, o0) of the four cells at constant offsets from one base
-            unsigned long long* b0 = hv + (iy0 * 4 + ix0) * 8 + o0;
+            // word (cell, o0) of the four cells at constant offsets from one
+            // base at cell 4 iy0 + ix0, clamped to -5 .. 15 so that the base
+            // stays within the histogram and the pad before it (an index
+            // that needs the clamp has no cell in range)
+            unsigned long long* b0 = hv + min(max(iy0 * 4 + ix0, -5), 15) * 8 + o0;
 #pragma unroll
             for (int jy = 0; jy < 2; ++jy) {
                 if ((unsigned)(iy0 + jy) > 3u) continue;
