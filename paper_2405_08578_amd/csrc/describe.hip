@@ -327,12 +327,10 @@ constexpr int kHalfMaxVisits = 700;
 constexpr int kHalfCopies = 2;
 // Histogram copies per wave: lane l votes into copy l mod kCopies, so the
 // neighbouring pixels that neighbouring lanes visit rarely hit one address
-// at once; the copies are summed when read (integer sums: order-free). The
-// single-orientation whole-wavefront kernel serves the scales with large
-// cells, where neighbouring pixels share a cell and mostly a direction bin: 4
-// copies there (measured 1.8 % faster than 2 despite 7 instead of 8
-// workgroups per CU); the multi-orientation passes, which also take the
-// smallest scale and clear the histograms per row, keep 2.
+// at once; the copies are summed when read (integer sums: order-free). With
+// a cell's two direction bins in one atomic, 2 copies measured faster than 4
+// in the whole-wavefront kernel (4 leave room for 7 workgroups per CU, 2 for
+// 8), and 1 slower than 2 in the half-wavefront kernel.
 constexpr int kCopies = 2;
 
 __device__ inline float wave_sum(float v)
@@ -393,9 +391,6 @@ __device__ inline void hist_sync()
 // slot); descriptors at the angles that pass stored, rows compacted.
 enum { kModeFull = 0, kModeOrient = 1, kModeGiven = 2 };
 
-// Histogram copies of the whole-wavefront kernel by mode (see kCopies).
-template <int kMode>
-constexpr int mode_copies() { return kMode == kModeFull ? 4 : kCopies; }
 
 // Smoothed 36-bin orientation histogram of one keypoint; lane k < 36 returns
 // bin k, other lanes -1. Ends with the votes visible to the whole wave.
@@ -634,7 +629,7 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
 template <int kMode>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void orient_describe_kernel(DescArgs a, const float4* tables)
 {
-    constexpr int kC = mode_copies<kMode>();
+    constexpr int kC = kCopies;
     __shared__ unsigned long long hist_mem[kCellPad + kWaves * kC * kBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long* hist = hist_mem + kCellPad + wave * kC * kBins;
