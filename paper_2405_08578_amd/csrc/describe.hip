@@ -346,8 +346,11 @@ constexpr int kMaxOrient = 4;      // orientations per keypoint (multi-orientati
 // than whole wavefronts there, slower once L = 32 is included).
 constexpr int kHalfMaxVisits = 700;
 // Histogram copies per half wavefront (even and odd lanes, as in the whole-
-// wavefront kernel).
+// wavefront kernel), of 128 bins each: the orientation histogram takes the
+// first 36 bins of each copy and is cleared after it is read, which keeps
+// the workgroup's LDS within 1/8 of the CU's (8 workgroups per CU).
 constexpr int kHalfCopies = 2;
+constexpr int kHalfWords = 128;
 // Histogram copies per wave: lane l votes into copy l mod kCopies, so the
 // neighbouring pixels that neighbouring lanes visit rarely hit one address
 // at once; the copies are summed when read (integer sums: order-free). With
@@ -437,7 +440,7 @@ __device__ inline float parabola_offset(float hm, float h0, float hp)
 // Orientation votes of one keypoint into ho[0..36) of each histogram copy;
 // its kStride lanes (sub = 0 .. kStride - 1) take table entries sub,
 // sub + kStride, ...
-template <int kStride, int kC = kCopies>
+template <int kStride, int kC = kCopies, int kW = kBins>
 __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bool live, int kx,
                                              int ky, const float2* field, int W, int H,
                                              const ScaleGeom& G, const float4* tables)
@@ -445,7 +448,7 @@ __device__ __forceinline__ void orient_votes(unsigned long long* ho, int sub, bo
     const int n = live ? G.n_orient : 0;
     const int per = (n + kStride - 1) / kStride;
     const float4* tab = tables + G.off_orient;
-    unsigned long long* hv = ho + (sub % kC) * kBins;   // this lane's copy
+    unsigned long long* hv = ho + (sub % kC) * kW;   // this lane's copy
     for (int it0 = 0; it0 < per; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
@@ -539,7 +542,7 @@ __device__ inline float peak_turns(float sm, int k, float h0)
 // Descriptor votes of one keypoint at angle th_turns into hist[0..128) of
 // each histogram copy (the packed layout read by desc_bin); lanes as in
 // orient_votes.
-template <int kStride, int kC = kCopies>
+template <int kStride, int kC = kCopies, int kW = kBins>
 __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bool live, int kx,
                                            int ky, const float2* field, int W, int H,
                                            const ScaleGeom& G, const float4* tables,
@@ -555,7 +558,7 @@ __device__ __forceinline__ void desc_votes(unsigned long long* hist, int sub, bo
     const int nd = live ? bcount[bk] : 0;
     const int perd = (nd + kStride - 1) / kStride;
     const float4* tabd = tables + G.off_desc + (int64_t)bk * G.cap_desc;
-    unsigned long long* hv = hist + (sub % kC) * kBins;   // this lane's copy
+    unsigned long long* hv = hist + (sub % kC) * kW;   // this lane's copy
     for (int it0 = 0; it0 < perd; it0 += kUnroll) {
         int dx[kUnroll], dy[kUnroll];
         bool ok[kUnroll];
@@ -801,11 +804,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void orient_describe_half_kernel(DescArgs a, const float4* tables)
 {
-    __shared__ unsigned long long hist_mem[kCellPad + kWaves * 2 * kHalfCopies * kBins];
+    __shared__ unsigned long long hist_mem[kCellPad + kWaves * 2 * kHalfCopies * kHalfWords];
     __shared__ float smv[kWaves][2][36];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int hf = lane >> 5, sub = lane & 31;
-    unsigned long long* hist = hist_mem + kCellPad + (wave * 2 + hf) * kHalfCopies * kBins;
+    unsigned long long* hist = hist_mem + kCellPad + (wave * 2 + hf) * kHalfCopies * kHalfWords;
     float* sv = smv[wave][hf];
 
     // this half's keypoint in its XCD's band list of the small scales
@@ -842,22 +845,29 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     const float2* field = I.field;
     const int W = I.w, H = I.h;
 
-    for (int b = sub; b < kHalfCopies * kBins; b += 32) hist[b] = 0ull;
+    for (int b = sub; b < kHalfCopies * kHalfWords; b += 32) hist[b] = 0ull;
     wave_sync();
 
     // ---- orientation ----
-    orient_votes<32, kHalfCopies>(hist + 128, sub, live, kx, ky, field, W, H, G, tables);
+    orient_votes<32, kHalfCopies, kHalfWords>(hist, sub, live, kx, ky, field, W, H, G, tables);
     wave_sync();
     auto bin = [&](int k) {
         unsigned long long v = 0ull;
 #pragma unroll
-        for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kBins + 128 + k];
+        for (int c = 0; c < kHalfCopies; ++c) v += hist[c * kHalfWords + k];
         return (float)v * kOrientVoteInv;
     };
     // each bin converted once: lane sub holds bin sub (ha) and, for sub < 4,
     // bin 32 + sub (hb); a neighbour bin comes from the lane that holds it
     const float ha = bin(sub);
     const float hb = sub < 4 ? bin(32 + sub) : 0.0f;
+    // each lane clears the orientation bins it read (the descriptor votes
+    // come after the next wave_sync)
+#pragma unroll
+    for (int c = 0; c < kHalfCopies; ++c) {
+        hist[c * kHalfWords + sub] = 0ull;
+        if (sub < 4) hist[c * kHalfWords + 32 + sub] = 0ull;
+    }
     auto at = [&](int b) {           // bin b (0 .. 35) of this half's histogram
         const float va = __shfl(ha, b & 31, 32);
         const float vb = __shfl(hb, (b - 32) & 31, 32);
@@ -897,7 +907,7 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     // The norms add (e, e + 64) pairs first, then the halves, then butterflies
     // over 32 lanes: the summation tree of wave_sum in the whole-wave kernel,
     // so both kernels give bit-identical descriptors.
-    desc_votes<32, kHalfCopies>(hist, sub, live, kx, ky, field, W, H, G, tables,
+    desc_votes<32, kHalfCopies, kHalfWords>(hist, sub, live, kx, ky, field, W, H, G, tables,
                                 a.bcount + sc * kDescBuckets, th_turns);
     wave_sync();
     float d[4];
@@ -905,7 +915,7 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     for (int q = 0; q < 4; ++q) {
         unsigned long long v = 0ull;
 #pragma unroll
-        for (int c = 0; c < kHalfCopies; ++c) v += desc_bin(hist + c * kBins, sub + 32 * q);
+        for (int c = 0; c < kHalfCopies; ++c) v += desc_bin(hist + c * kHalfWords, sub + 32 * q);
         d[q] = (float)v * G.dinv;
     }
     auto half_norm = [&]() {
