@@ -252,8 +252,11 @@ __device__ inline float polar_turns(int y, int x)
 // One launch builds the disc tables and the gradient fields: workgroups
 // 0 .. n_table - 1 take the table jobs (dispatched first, so the few long
 // table jobs run beside the many short field rows instead of after them);
-// workgroup n_table + (z gy + y) gx + x then takes the row segment of 256
-// pixels at column 256 x of row y of image z.
+// workgroup n_table + (z gy + y) gx + x then takes the row segment of
+// 256 kFieldPx pixels at column 256 kFieldPx x of row y of image z, thread t
+// the pixels t + 256 k (coalesced; a few pixels per thread keep the waves
+// fewer than one per 64 pixels, whose launch rate bounded the field).
+constexpr int kFieldPx = 4;
 __global__ __launch_bounds__(256) void polar_field_kernel(FieldArgs a, TableArgs ta,
                                                           float4* tables, int32_t* counts,
                                                           int n_table, int gx, int gy)
@@ -271,18 +274,26 @@ __global__ __launch_bounds__(256) void polar_field_kernel(FieldArgs a, TableArgs
     const int z = f / (gx * gy), rem = f - z * (gx * gy);
     const FieldImg& I = a.img[z];
     const int r = rem / gx;
-    const int c = (rem - r * gx) * 256 + threadIdx.x;
-    if (r >= I.h || c >= I.w) return;
-    float2 out = make_float2(0.0f, 0.0f);
-    if (r >= 1 && r <= I.h - 2 && c >= 1 && c <= I.w - 2) {
-        const uint8_t* p = I.data + (int64_t)r * I.pitch + c;
-        const int av = (int)p[I.pitch] - (int)p[-I.pitch];   // along rows
-        const int bv = (int)p[1] - (int)p[-1];               // along columns
-        const int n2 = av * av + bv * bv;
-        // v_sqrt_f32 (within 1 ulp) of the integer sum, the angle above
-        if (n2 > 0) out = make_float2(__builtin_amdgcn_sqrtf((float)n2), polar_turns(av, bv));
+    if (r >= I.h) return;
+    const int c0 = (rem - r * gx) * (256 * kFieldPx) + threadIdx.x;
+    const bool row_in = r >= 1 && r <= I.h - 2;
+    const uint8_t* prow = I.data + (int64_t)r * I.pitch;
+    float2* frow = I.field + (int64_t)r * I.w;
+#pragma unroll
+    for (int k = 0; k < kFieldPx; ++k) {
+        const int c = c0 + 256 * k;
+        if (c >= I.w) break;
+        float2 out = make_float2(0.0f, 0.0f);
+        if (row_in && c >= 1 && c <= I.w - 2) {
+            const uint8_t* p = prow + c;
+            const int av = (int)p[I.pitch] - (int)p[-I.pitch];   // along rows
+            const int bv = (int)p[1] - (int)p[-1];               // along columns
+            const int n2 = av * av + bv * bv;
+            // v_sqrt_f32 (within 1 ulp) of the integer sum, the angle above
+            if (n2 > 0) out = make_float2(__builtin_amdgcn_sqrtf((float)n2), polar_turns(av, bv));
+        }
+        frow[c] = out;
     }
-    I.field[(int64_t)r * I.w + c] = out;
 }
 
 // ------------------------------------------------------ orient + describe --
@@ -1114,7 +1125,7 @@ int run_describe(const lpsift_image* imgs, int n, const lpsift_keypoints* kps, c
         }
         {
             TimedScope ts(LPSIFT_KERNEL_GRADIENT, stream);
-            const int gx = (maxw + 255) / 256;
+            const int gx = (maxw + 256 * kFieldPx - 1) / (256 * kFieldPx);
             const int64_t blocks = (int64_t)n_table + (int64_t)gx * maxh * nb;
             hipLaunchKernelGGL(polar_field_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, fa,
                                ta, tables, bcount, n_table, gx, maxh);
