@@ -393,15 +393,25 @@ __device__ inline int floor_int(float x)
     return r;
 }
 
-// Descriptor bin b (cell b / 8, direction b % 8) of one histogram copy: the
-// votes of visits whose lower direction bin is o sit in 64-bit word
-// (cell, o), for bin o in its low and for bin o + 1 (mod 8) in its high
-// 32-bit word.
-__device__ inline unsigned long long desc_bin(const unsigned long long* h, int b)
+// Descriptor bin b (cell b / 8, direction b % 8) over kC histogram copies
+// of kW words, in vote units before the scale: the votes of visits whose
+// lower direction bin is o sit in 64-bit word (cell, o), for bin o in its
+// low and for bin o + 1 (mod 8) in its high 32-bit word. Each word converts
+// to float exactly to 24 bits and the 2 kC parts add in this fixed order, so
+// every kernel reads the same value (within 3e-7 relative of the integer
+// total).
+template <int kC, int kW>
+__device__ inline float desc_bin(const unsigned long long* h, int b)
 {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(h);
     const int prev = (b & ~7) | ((b + 7) & 7);
-    return (unsigned long long)w[2 * b] + (unsigned long long)w[2 * prev + 1];
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) {
+        s += (float)w[2 * (c * kW + b)];
+        s += (float)w[2 * (c * kW + prev) + 1];
+    }
+    return s;
 }
 
 // Makes a wave's LDS writes visible to its own later reads. Enough where each
@@ -445,7 +455,13 @@ __device__ inline float smooth5(float h2m, float h1m, float h0, float h1p, float
 __device__ inline float parabola_offset(float hm, float h0, float hp)
 {
     const float den = fmaf(-2.0f, h0, hm) + hp;
-    return (den != 0.0f) ? 0.5f * (hm - hp) / den : 0.0f;
+    return (den != 0.0f) ? 0.5f * (hm - hp) * __builtin_amdgcn_rcpf(den) : 0.0f;
+}
+
+// Angle in turns of orientation bin k refined by the parabola offset.
+__device__ inline float bin_turns(int k, float hm, float h0, float hp)
+{
+    return ((float)k + parabola_offset(hm, h0, hp)) * (1.0f / 36.0f);
 }
 
 // Orientation votes of one keypoint into ho[0..36) of each histogram copy;
@@ -544,7 +560,7 @@ __device__ inline float peak_turns(float sm, int k, float h0)
 {
     const float hm = __shfl(sm, (k + 35) % 36);
     const float hp = __shfl(sm, (k + 1) % 36);
-    return ((float)k + parabola_offset(hm, h0, hp)) / 36.0f;
+    return bin_turns(k, hm, h0, hp);
 }
 
 // Descriptor of one keypoint at angle th_turns: votes into hist[0..128),
@@ -648,13 +664,8 @@ __device__ __forceinline__ void describe_at(unsigned long long* hist, int lane, 
     desc_votes<64, kC>(hist, lane, live, kx, ky, field, W, H, G, tables, bcount, th_turns);
     hist_sync<kWaveOnly>();
     const float dinv = G.dinv;
-    unsigned long long s0 = 0ull, s1 = 0ull;
-#pragma unroll
-    for (int c = 0; c < kC; ++c) {
-        s0 += desc_bin(hist + c * kBins, lane);
-        s1 += desc_bin(hist + c * kBins, lane + 64);
-    }
-    float d0 = (float)s0 * dinv, d1 = (float)s1 * dinv;
+    float d0 = desc_bin<kC, kBins>(hist, lane) * dinv;
+    float d1 = desc_bin<kC, kBins>(hist, lane + 64) * dinv;
     float inv = __builtin_amdgcn_rcpf(fmaxf(sqrtf(wave_sum(fmaf(d0, d0, d1 * d1))), 1e-12f));
     d0 = fminf(d0 * inv, 0.2f);
     d1 = fminf(d1 * inv, 0.2f);
@@ -677,7 +688,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     if (kMode == kModeFull && a.list) {
         // list mode: entries of every image in turn, each list from its end
         // (largest slots, i.e. largest scale, first); output at the entry
-        int64_t j = (int64_t)blockIdx.x * kWaves + wave;
+        int64_t j = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(wave);
         for (int i = 0; i < a.n_images; ++i) {
             if (j < a.img[i].n_sel) {
                 im = i;
@@ -698,7 +709,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         // locate (scale, image, slot) of this wave's keypoint in its XCD's band list
         // (32-bit arithmetic: window counts and slots of one image are < 2^31)
         const int xcd = blockIdx.x % kXcds;
-        int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + wave;
+        int64_t j = (int64_t)(blockIdx.x / kXcds) * kWaves + __builtin_amdgcn_readfirstlane(wave);
         for (int so = 0; so < a.n_scales - a.first_scale && !live; ++so) {
             const int s = a.n_scales - 1 - so;
             const uint32_t L = (uint32_t)a.L[s];
@@ -822,13 +833,18 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     unsigned long long* hist = hist_mem + kCellPad + (wave * 2 + hf) * kHalfCopies * kHalfWords;
     float* sv = smv[wave][hf];
 
-    // this half's keypoint in its XCD's band list of the small scales
+    // this half's keypoint in its XCD's band list of the small scales. The
+    // wave's two halves take entries 2 m and 2 m + 1 of the list, and every
+    // (scale, image) band holds an even number of entries (a max and a min
+    // per window), so both halves fall in one band: the search runs once
+    // per wave, in scalar registers, and the halves differ by their slot.
     bool live = false;
     int sc = 0, im = 0;
     int64_t slot = 0;
     {
         const int xcd = blockIdx.x % kXcds;
-        int64_t j = (int64_t)(blockIdx.x / kXcds) * (2 * kWaves) + 2 * wave + hf;
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        int64_t j = (int64_t)(blockIdx.x / kXcds) * (2 * kWaves) + 2 * wv;
         for (int so = 0; so < a.half_scales && !live; ++so) {
             const int s = a.half_scales - 1 - so;
             const uint32_t L = (uint32_t)a.L[s];
@@ -849,7 +865,7 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
             }
         }
     }
-    if (!live) slot = 0;
+    slot = live ? slot + hf : 0;
     const DescImg& I = a.img[im];
     const ScaleGeom G = a.geom[sc];   // a copy: its fields stay in registers through the visit loops
     const int kx = I.x[slot], ky = I.y[slot];
@@ -911,7 +927,7 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     }
     wave_sync();
     const float hm = sv[(bk + 35) % 36], hp = sv[(bk + 1) % 36];
-    const float th_turns = ((float)bk + parabola_offset(hm, bv, hp)) / 36.0f;
+    const float th_turns = bin_turns(bk, hm, bv, hp);
     if (live && sub == 0) I.theta[slot] = th_turns * 6.283185307179586f;
 
     // ---- descriptor: lane sub holds elements sub + 32 q ----
@@ -923,12 +939,7 @@ void orient_describe_half_kernel(DescArgs a, const float4* tables)
     wave_sync();
     float d[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        unsigned long long v = 0ull;
-#pragma unroll
-        for (int c = 0; c < kHalfCopies; ++c) v += desc_bin(hist + c * kHalfWords, sub + 32 * q);
-        d[q] = (float)v * G.dinv;
-    }
+    for (int q = 0; q < 4; ++q) d[q] = desc_bin<kHalfCopies, kHalfWords>(hist, sub + 32 * q) * G.dinv;
     auto half_norm = [&]() {
         float ss = fmaf(d[0], d[0], d[2] * d[2]) + fmaf(d[1], d[1], d[3] * d[3]);
 #pragma unroll
