@@ -197,6 +197,11 @@ size_t lpsift_describe_workspace_size(const lpsift_image* imgs, int32_t n_images
  *          trilinear votes into 4 x 4 cells x 8 direction bins (bin o centred at
  *          45 o degrees from theta), element (cy*4 + cx)*8 + o; then normalised,
  *          clipped at 0.2 and normalised again (all zeros for a flat patch).
+ * Arithmetic: FP32, histograms summed as fixed-point integers (results are
+ * identical from run to run and do not depend on the order of the votes);
+ * descriptors within 1e-4 relative L2 and theta within 1e-4 rad of an FP64
+ * evaluation, except where the two highest smoothed orientation bins tie to
+ * within 1e-5 relative.
  *  kps        host array of n_images keypoint buffers written by lpsift_detect
  *  workspace  device buffer of ws_bytes >= lpsift_describe_workspace_size()
  *  theta      host array of n_images device pointers to float[n_kp]
