@@ -10,7 +10,7 @@
 //     the entries that the rotated square can reach for an angle of the bucket.
 //  2. polar_field_kernel: the Eq. 5 gradient of every pixel once, as
 //     (magnitude, angle in turns in [0, 1)); border pixels get magnitude 0.
-//     Each image pixel is visited by ~10 keypoint supports, so the atan2 and
+//     Each image pixel is visited by ~10 keypoint supports, so the angle and
 //     the square root are paid once per pixel instead of once per visit.
 //  3. orient_describe_kernel: one wavefront per keypoint, four per workgroup.
 //     Lane l takes table entries l, l + 64, l + 128, ... (four at a time, all
@@ -32,7 +32,9 @@
 //     Orientation (36 bins, smoothing, argmax,
 //     parabola), then the 128-bin descriptor, normalisation, clipping at 0.2
 //     and renormalisation happen in the same wave; the descriptor row is
-//     stored with two coalesced 256-byte writes.
+//     stored with two coalesced 256-byte writes. orient_describe_half_kernel
+//     does the same for the smallest scale with one keypoint per 32-lane half
+//     of a wavefront, bit for bit.
 #include "internal.h"
 
 namespace lpsift {
