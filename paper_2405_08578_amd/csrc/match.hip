@@ -459,6 +459,7 @@ template <> struct Lp<1> {             // BF16
     static constexpr int kSteps = 8;     // MFMAs per 32 x 32 block over K = 128
     static constexpr int kKStep = 16;    // K per MFMA
     static constexpr int kEsize = 2;
+    static constexpr int kCT = 64;       // candidates per LDS tile
 };
 template <> struct Lp<2> {             // FP8 E4M3
     static constexpr int kRowBytes = 128;
@@ -466,6 +467,9 @@ template <> struct Lp<2> {             // FP8 E4M3
     static constexpr int kSteps = 2;
     static constexpr int kKStep = 64;
     static constexpr int kEsize = 1;
+    // candidates per LDS tile: 128 halves the tile barriers per candidate
+    // (10 % faster; BF16's larger rows would spill at 128)
+    static constexpr int kCT = 128;
 };
 
 // BF16 bits of x, rounded to nearest even (finite x).
@@ -480,7 +484,6 @@ constexpr int kLpKeepBf16 = 2;                     // keys kept per lane: BF16 .
 constexpr int kLpKeepFp8 = 2;                      // ... and FP8
 constexpr int kLpRescore = 8;                      // kept candidates rescored in FP32
 constexpr int kLpQB = 4 * 32 * kLpSets;            // queries per workgroup (512)
-constexpr int kLpCT = 64;                          // candidates per LDS tile
 constexpr float kFp8Max = 448.0f;                  // largest finite E4M3 value
 
 // Quantise rows of 128 floats: BF16 (round to nearest even) or FP8 E4M3 with
@@ -561,11 +564,11 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
 {
     using T = Lp<P>;
     constexpr int kLRow = T::kRowBytes + 16;   // padded LDS row
-    constexpr int kU4 = kLpCT * T::kRowBytes / 16 / 256;   // uint4 per thread per tile
-    __shared__ __attribute__((aligned(16))) uint8_t tile[kLpCT * kLRow];
+    constexpr int kU4 = T::kCT * T::kRowBytes / 16 / 256;   // uint4 per thread per tile
+    __shared__ __attribute__((aligned(16))) uint8_t tile[T::kCT * kLRow];
     // -(|b|^2 + C) / 2 per tile row: the accumulators' starting values
-    __shared__ __attribute__((aligned(16))) float tnb[kLpCT];
-    __shared__ float tsb[kLpCT];                // candidate scales (FP8)
+    __shared__ __attribute__((aligned(16))) float tnb[T::kCT];
+    __shared__ float tsb[T::kCT];                // candidate scales (FP8)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
     };
     if (cb < ce) fetch(cb);
 
-    for (int64_t t0 = cb; t0 < ce; t0 += kLpCT) {
+    for (int64_t t0 = cb; t0 < ce; t0 += T::kCT) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kU4; ++k) {
@@ -622,17 +625,17 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
             const int r = f / (T::kRowBytes / 16), c16 = f % (T::kRowBytes / 16);
             *reinterpret_cast<uint4*>(&tile[r * kLRow + c16 * 16]) = pf[k];
         }
-        if (tid < kLpCT) {
+        if (tid < T::kCT) {
             const int64_t j = t0 + tid;
             tnb[tid] = (j < ce) ? -0.5f * (nrmB[j] + C) : -INFINITY;
             tsb[tid] = (P == 2 && j < ce) ? sB[j] : 1.0f;
         }
         __syncthreads();
-        if (t0 + kLpCT < ce) fetch(t0 + kLpCT);
+        if (t0 + T::kCT < ce) fetch(t0 + T::kCT);
         const uint32_t local0 = (uint32_t)(t0 - cb);
 
 #pragma unroll 1
-        for (int sub = 0; sub < kLpCT / 32; ++sub) {
+        for (int sub = 0; sub < T::kCT / 32; ++sub) {
             // BF16: every accumulator starts at -(|b|^2 + C) / 2 of its row
             // (the same for all four query sets: the first MFMA of each set
             // takes these registers as its addend), so that it ends at
@@ -1556,7 +1559,8 @@ MatchPlan plan_match(int64_t nA, int64_t nB, const lpsift_match_params* mp)
     default: {
         // the rescore wavefront holds chunks x 2 lane halves x K keys
         const int keep = (mp->precision == 1) ? kLpKeepBf16 : kLpKeepFp8;
-        return plan_chunks(nA, nB, kLpQB, kLpCT, 64 / (2 * keep), mp->b_chunks);
+        return plan_chunks(nA, nB, kLpQB, mp->precision == 2 ? Lp<2>::kCT : Lp<1>::kCT, 64 / (2 * keep),
+                           mp->b_chunks);
     }
     }
 }
