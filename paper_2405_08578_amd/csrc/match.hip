@@ -654,6 +654,10 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
             }
             floatx16 acc[kLpSets];
             const uint8_t* trow = &tile[(sub * 32 + col) * kLRow];
+            // FP8: the wave issuing its MFMAs takes precedence over the other
+            // wave of the SIMD (in its epilogue), which keeps the matrix core
+            // fed (measured 2-4 % faster; no change for BF16)
+            if constexpr (P == 2) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < T::kSteps; ++s) {
                 uint4 av[kQRegs];
@@ -679,6 +683,7 @@ __global__ __launch_bounds__(256, 2) void match_topk_lp_kernel(
                     }
                 }
             }
+            if constexpr (P == 2) __builtin_amdgcn_s_setprio(0);
             // epilogue: key = (accumulator bits & ~mask) | index in chunk.
             // The accumulators are negative, so their bits (sign set) order
             // like their magnitudes, i.e. like the scores; top-K by min /
