@@ -125,12 +125,12 @@ typedef struct lpsift_keypoints {
  *  precision   contraction used to select candidates (d1 and d2 are always
  *              direct FP32 distances of the selected candidates):
  *              0 = FP32 matrix cores; exact up to FP32 rounding.
- *              1 = BF16 inputs, FP32 accumulation; the 8 best kept candidates
- *                  per query are rescored: approximate (a true nearest
+ *              1 = BF16 inputs, FP32 accumulation; the topk best kept
+ *                  candidates per query are rescored: approximate (a true nearest
  *                  neighbour can be missed; ties are resolved to the lowest
  *                  index among the rescored candidates).
  *              2 = FP8 E4M3 inputs with one scale per descriptor, FP32
- *                  accumulation, 8 candidates rescored: approximate.
+ *                  accumulation, topk candidates rescored: approximate.
  *              3 = FP32 split into two BF16 parts (three BF16 products per
  *                  term, FP32 accumulation), certified per query by an error
  *                  bound; queries it cannot certify are re-matched with
@@ -142,6 +142,11 @@ typedef struct lpsift_keypoints {
  *  qblock_waves  wavefronts per workgroup of the FP32 contraction (precision 0
  *              and precision 3's re-match), each holding 64 queries: 0 =
  *              automatic (4), or 2, 4, 8; every value gives the same lists
+ *  topk        precisions 1 and 2: the number of best candidates by the
+ *              reduced-precision contraction that are rescored in FP32 per
+ *              query, 2 .. 8 (0 = 8); fewer is faster to rescore and misses
+ *              more true neighbours. Must be 0 at precisions 0 and 3, whose
+ *              candidate selection is exact.
  *  stats       optional device pointer to one uint32: after the call (stream
  *              order) it holds the number of queries, summed over all pairs,
  *              that precision 3 re-matched with precision 0 (0 otherwise) */
@@ -151,6 +156,7 @@ typedef struct lpsift_match_params {
     int32_t precision;
     int32_t b_chunks;
     int32_t qblock_waves;
+    int32_t topk;
     void* stats;
 } lpsift_match_params;
 

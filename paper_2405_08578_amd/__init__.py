@@ -53,7 +53,7 @@ class lpsift_ransac_params(ctypes.Structure):
 
 class lpsift_match_params(ctypes.Structure):
     _fields_ = [("ratio", c_f64), ("abs_thresh", c_f32), ("precision", c_i32),
-                ("b_chunks", c_i32), ("qblock_waves", c_i32), ("stats", c_vp)]
+                ("b_chunks", c_i32), ("qblock_waves", c_i32), ("topk", c_i32), ("stats", c_vp)]
 
 
 EXPORTS = ("lpsift_version", "lpsift_status_string", "lpsift_num_keypoints", "lpsift_detect",
@@ -316,13 +316,15 @@ def describe(images, kps, params: Params, workspace=None, theta=None, desc=None,
 
 
 def match_params(ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
-                 b_chunks: int = 0, stats=None, qblock_waves: int = 0) -> lpsift_match_params:
+                 b_chunks: int = 0, stats=None, qblock_waves: int = 0,
+                 topk: int = 0) -> lpsift_match_params:
     mp = lpsift_match_params()
     mp.ratio = ratio
     mp.abs_thresh = abs_thresh
     mp.precision = precision
     mp.b_chunks = b_chunks
     mp.qblock_waves = qblock_waves
+    mp.topk = topk
     mp.stats = None if stats is None else stats.data_ptr()
     return mp
 
@@ -366,13 +368,14 @@ def _match_args(descA, descB, out, workspace, need, stream=None):
 
 def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precision: int = 0,
           b_chunks: int = 0, workspace=None, out=None, stream=None,
-          stats=None, qblock_waves: int = 0) -> List[Dict[str, "object"]]:
+          stats=None, qblock_waves: int = 0, topk: int = 0) -> List[Dict[str, "object"]]:
     """Nearest neighbour of every row of descA[p] among descB[p] with the ratio
     test, for every pair p. stats: optional int32 CUDA tensor [1] that receives
     the number of queries the split path re-matched in FP32 (sum over pairs).
-    b_chunks, qblock_waves: the work split (0 = automatic; see match_tune)."""
+    b_chunks, qblock_waves: the work split (0 = automatic; see match_tune).
+    topk: candidates rescored per query at precisions 1 and 2 (0 = 8)."""
     lib = load()
-    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats, qblock_waves)
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats, qblock_waves, topk)
     out, head, tail = _match_args(descA, descB, out, workspace,
                                   lambda nA, nB: match_workspace_size(nA, nB, mp), stream)
     _check("lpsift_match", lib.lpsift_match(*head, ctypes.byref(mp), *tail, _stream(stream)))
@@ -381,12 +384,12 @@ def match(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf, precis
 
 def match_noalloc(descA, descB, ratio: float = 0.8, abs_thresh: float = math.inf,
                   precision: int = 0, b_chunks: int = 0, out=None, stream=None,
-                  stats=None, qblock_waves: int = 0) -> List[Dict[str, "object"]]:
+                  stats=None, qblock_waves: int = 0, topk: int = 0) -> List[Dict[str, "object"]]:
     """match() through lpsift_match_noalloc: the library's fixed per-device
     scratch array is the workspace, so with `out` given nothing is allocated.
     Calls that overlap on one device race on that array."""
     lib = load()
-    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats, qblock_waves)
+    mp = match_params(ratio, abs_thresh, precision, b_chunks, stats, qblock_waves, topk)
     out, head, tail = _match_args(descA, descB, out, None, None, stream)
     _check("lpsift_match_noalloc",
            lib.lpsift_match_noalloc(*head, ctypes.byref(mp), *tail[2:], _stream(stream)))

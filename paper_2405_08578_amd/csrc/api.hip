@@ -368,6 +368,9 @@ static int check_match_params(const lpsift_match_params* mp)
         mp->qblock_waves != 8)
         return LPSIFT_EINVAL;
     if (mp->precision < 0 || mp->precision > 3) return LPSIFT_EINVAL;
+    // the ratio test needs a second rescored candidate: topk 2 .. 8
+    if (mp->topk != 0 && (mp->topk < 2 || mp->topk > 8)) return LPSIFT_EINVAL;
+    if (mp->topk != 0 && (mp->precision == 0 || mp->precision == 3)) return LPSIFT_EINVAL;
     return LPSIFT_OK;
 }
 

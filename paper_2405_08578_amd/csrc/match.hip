@@ -739,7 +739,7 @@ template <int K>
 __global__ __launch_bounds__(256) void rescore_lp_kernel(
     const float* __restrict__ A, int64_t nA, const float* __restrict__ B, int chunks,
     int64_t chunk_len, uint32_t idx_mask, const uint32_t* __restrict__ keys, double ratio,
-    float abs_thresh, int32_t* __restrict__ match, float* __restrict__ d1out,
+    float abs_thresh, int n_rescore, int32_t* __restrict__ match, float* __restrict__ d1out,
     float* __restrict__ d2out)
 {
     // 16 lanes per query, four queries per wavefront (see rescore_f32_query)
@@ -764,7 +764,8 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
             }
         }
     }
-    // the kLpRescore best kept keys (ties: lower entry first), selected first ...
+    // the n_rescore <= kLpRescore best kept keys (ties: lower entry first),
+    // selected first ...
     int64_t pick[kLpRescore];
     int cnt = 0;
 #pragma unroll
@@ -786,7 +787,7 @@ __global__ __launch_bounds__(256) void rescore_lp_kernel(
                 be = oe;
             }
         }
-        if (bs != INFINITY) cnt = round + 1;
+        if (bs != INFINITY && round < n_rescore) cnt = round + 1;
         int64_t jj = -1;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -1627,8 +1628,8 @@ int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStre
         }
         TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);
         hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepBf16>), gr, dim3(256), 0, stream, A, nA, B,
-                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, io.match,
-                           io.d1, io.d2);
+                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh,
+                           mp->topk ? mp->topk : kLpRescore, io.match, io.d1, io.d2);
     } else {
         hipLaunchKernelGGL(quantize_kernel<2>, gq, dim3(256), 0, stream, A, nA, aq, sa,
                            (uint32_t*)nullptr);
@@ -1642,8 +1643,8 @@ int launch_lp_pair(const MatchPairIO& io, const lpsift_match_params* mp, hipStre
         }
         TimedScope ts(LPSIFT_KERNEL_MATCH_RESCORE, stream);
         hipLaunchKernelGGL((rescore_lp_kernel<kLpKeepFp8>), gr, dim3(256), 0, stream, A, nA, B,
-                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh, io.match,
-                           io.d1, io.d2);
+                           p.chunks, p.chunk_len, mask, keys, mp->ratio, mp->abs_thresh,
+                           mp->topk ? mp->topk : kLpRescore, io.match, io.d1, io.d2);
     }
     return hipGetLastError() == hipSuccess ? LPSIFT_OK : LPSIFT_EHIP;
 }

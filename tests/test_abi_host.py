@@ -153,8 +153,15 @@ def test_match_validation_and_workspace(lib):
                 lp.match_params(abs_thresh=math.nan), lp.match_params(abs_thresh=-1.0),
                 lp.match_params(b_chunks=17), lp.match_params(precision=4),
                 lp.match_params(qblock_waves=3), lp.match_params(qblock_waves=16),
-                lp.match_params(qblock_waves=-1)):
+                lp.match_params(qblock_waves=-1),
+                # topk: 2 .. 8 at precisions 1 and 2 only
+                lp.match_params(precision=1, topk=1), lp.match_params(precision=2, topk=9),
+                lp.match_params(precision=1, topk=-1), lp.match_params(precision=0, topk=2),
+                lp.match_params(precision=3, topk=8)):
         assert call(bad) == lp.LPSIFT_EINVAL
+    for prec in (1, 2):
+        for k in (2, 5, 8):   # accepted: the workspace check comes next
+            assert call(lp.match_params(precision=prec, topk=k)) == lp.LPSIFT_ECAPACITY
     for w in (2, 4, 8):
         assert lp.match_workspace_size(nA, nB, lp.match_params(qblock_waves=w)) > 0
     # low-precision paths need more workspace (quantised copies, keys, FP32 fallback)

@@ -226,3 +226,31 @@ def test_config1_split_equals_fp32(gpu):
         marg = match_margins(g32["d1"][diff].astype(np.float64), g32["d2"][diff].astype(np.float64), 0.8)
         assert np.all(marg < 1e-5)
     assert len(diff) <= 3
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_quantised_topk(gpu, prec):
+    """topk (candidates rescored in FP32 per query): 8 is the default, bit for
+    bit; 2 still finds every query whose true two nearest the quantised oracle
+    guarantees, and wherever it recalls both its lists equal topk 8's, since
+    the rescored distances are the same FP32 values."""
+    A, B = sets(2000, 3000, 3)
+    say("quantised topk", prec)
+    g0 = run_match(gpu, A, B, precision=prec)
+    g8 = run_match(gpu, A, B, precision=prec, topk=8)
+    for k in ("match", "d1", "d2"):
+        assert np.array_equal(g0[k], g8[k])
+    g2 = run_match(gpu, A, B, precision=prec, topk=2)
+    rec1, rec12 = check_quantised_against_oracle(A, B, g2, prec, 0.5)
+    r1, r12 = check_quantised_against_oracle(A, B, g8, prec, 0.5)
+    assert rec12 <= r12 + 1e-12
+    o = oracle.match(A.astype(np.float64), B.astype(np.float64))
+    fin2 = np.isfinite(o["d2"])
+    tol = lambda d: 2e-6 * d + 1e-6
+    both = (np.abs(g2["d1"] - o["d1"]) <= tol(o["d1"])) & fin2 & \
+        (np.abs(g2["d2"] - np.where(fin2, o["d2"], 0)) <= tol(np.where(fin2, o["d2"], 0)))
+    both &= (np.abs(g8["d1"] - o["d1"]) <= tol(o["d1"])) & \
+        (np.abs(g8["d2"] - np.where(fin2, o["d2"], 0)) <= tol(np.where(fin2, o["d2"], 0)))
+    assert both.mean() > 0.5
+    for k in ("match", "d1", "d2"):
+        assert np.array_equal(g2[k][both], g8[k][both])
