@@ -35,11 +35,11 @@ CALLS = (
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", [0, 3, 1, 2])
-def test_noalloc_equals_workspace_call(gpu, precision):
+@pytest.mark.parametrize("precision,topk", [(0, 0), (3, 0), (1, 0), (2, 0), (1, 3), (2, 2)])
+def test_noalloc_equals_workspace_call(gpu, precision, topk):
     import torch
     for k, sizes in enumerate(CALLS):
-        say("match_noalloc", "precision", precision, "call", k, "sizes", sizes)
+        say("match_noalloc", "precision", precision, "topk", topk, "call", k, "sizes", sizes)
         sets = _sets(sizes, 7100 + 10 * precision + k)
         if k == 0 and len(sizes) > 1:
             sets[1] = (sets[1][0], sets[0][1])          # same registered set as pair 0
@@ -47,7 +47,7 @@ def test_noalloc_equals_workspace_call(gpu, precision):
         dB = [torch.from_numpy(b).to(gpu) for _, b in sets]
         if k == 0 and len(sizes) > 1:
             dB[1] = dB[0]                               # shared pointer: norms computed once
-        mp = lp.match_params(precision=precision)
+        mp = lp.match_params(precision=precision, topk=topk)
         assert lp.match_workspace_size([len(a) for a, _ in sets], [len(b) for _, b in sets],
                                        mp) <= lp.NOALLOC_SCRATCH_BYTES
         out = [{"match": torch.full((len(a),), -7, dtype=torch.int32, device=gpu),
@@ -56,8 +56,8 @@ def test_noalloc_equals_workspace_call(gpu, precision):
                for a, _ in sets]
         st_n = torch.zeros(1, dtype=torch.int32, device=gpu)
         st_r = torch.zeros(1, dtype=torch.int32, device=gpu)
-        got = lp.match_noalloc(dA, dB, precision=precision, out=out, stats=st_n)
-        ref = lp.match(dA, dB, precision=precision, stats=st_r)
+        got = lp.match_noalloc(dA, dB, precision=precision, out=out, stats=st_n, topk=topk)
+        ref = lp.match(dA, dB, precision=precision, stats=st_r, topk=topk)
         torch.cuda.synchronize()
         for p, (g, r) in enumerate(zip(got, ref)):
             for f in ("match", "d1", "d2"):
