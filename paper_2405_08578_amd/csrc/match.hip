@@ -146,6 +146,27 @@ __device__ inline uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
+// Minimum and median of three finite floats given as their bits (the
+// compiler's float min / med3 would first quiet each operand, rebuilt from
+// integer bits, as a possible NaN: one more instruction per operand).
+__device__ inline int fmin3_bits(int a, int b, int c)
+{
+    int r;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ inline int fmed3_bits(int a, int b, int c)
+{
+    int r;
+    asm("v_med3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// |b|^2 standing in for padded tile rows: finite, so their keys stay
+// ordinary floats, and above every real squared distance.
+constexpr float kPadNorm = 3.0e38f;
+
 // One (query block, chunk) work item of the FP32 contraction, kW wavefronts
 // of 64 queries each (a block of 64 kW queries). nq: number of queries;
 // qlist (optional) maps list entry i to its query row, results for entry i
@@ -159,7 +180,7 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
                                      int64_t qblk, int chunk)
 {
     __shared__ __attribute__((aligned(16))) float tile[kCT * kRow];
-    __shared__ float tnrm[kCT];
+    __shared__ __attribute__((aligned(16))) float tnrm[kCT];   // |b|^2 / 2 of the tile rows
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -171,8 +192,8 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     const uint32_t cb = (uint32_t)((int64_t)chunk * chunk_len);
     const uint32_t ce = (uint32_t)(((int64_t)cb + chunk_len < nB) ? (int64_t)cb + chunk_len : nB);
 
-    // queries in registers: qa[i] = A[q0][h*64 + i], qb[i] = A[q1][h*64 + i];
-    // na, nb: |a|^2 of the two queries
+    // queries in registers, negated: qa[i] = -A[q0][h*64 + i], qb[i] =
+    // -A[q1][h*64 + i]; na, nb: |a|^2 of the two queries
     float qa[64], qb[64];
     float na, nb;
     {
@@ -182,12 +203,15 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
         for (int i = 0; i < 16; ++i) {
             const float4 va = (q0 >= 0) ? pa[i] : make_float4(0.f, 0.f, 0.f, 0.f);
             const float4 vb = (q1 >= 0) ? pb[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            qa[4 * i + 0] = va.x; qa[4 * i + 1] = va.y; qa[4 * i + 2] = va.z; qa[4 * i + 3] = va.w;
-            qb[4 * i + 0] = vb.x; qb[4 * i + 1] = vb.y; qb[4 * i + 2] = vb.z; qb[4 * i + 3] = vb.w;
+            qa[4 * i + 0] = -va.x; qa[4 * i + 1] = -va.y; qa[4 * i + 2] = -va.z; qa[4 * i + 3] = -va.w;
+            qb[4 * i + 0] = -vb.x; qb[4 * i + 1] = -vb.y; qb[4 * i + 2] = -vb.z; qb[4 * i + 3] = -vb.w;
         }
         float sa = 0.0f, sb = 0.0f;
 #pragma unroll
         for (int i = 0; i < 64; ++i) {
+            // opaque from here on: the compiler would otherwise keep the
+            // loaded values and negate them again in every tile
+            asm volatile("" : "+v"(qa[i]), "+v"(qb[i]));
             sa = fmaf(qa[i], qa[i], sa);
             sb = fmaf(qb[i], qb[i], sb);
         }
@@ -195,14 +219,17 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
         nb = sb + __shfl_xor(sb, 32);
     }
 
-    // Each lane keeps the top-2 of its candidates as 32-bit keys: the bits of
-    // the squared distance (|a|^2 enters through the accumulator's initial
-    // value -|a|^2 / 2) with the low 4 bits replaced by the accumulator row r,
-    // compared as signed integers (non-negative floats order like their bits;
-    // a distance rounded below zero sorts first). A key is kept with a min and
-    // a med3; the tile of each kept key is recovered once per tile by comparing
-    // the keys with their values before the tile.
-    int ka1 = 0x7FFFFFFF, ka2 = 0x7FFFFFFF, kb1 = 0x7FFFFFFF, kb2 = 0x7FFFFFFF;
+    // Every accumulator starts at |b|^2 / 2 of its row (the same registers for
+    // both queries: the first MFMA takes them as its addend) and ends at
+    // |b|^2 / 2 - a.b = (|a - b|^2 - |a|^2) / 2, which orders the candidates
+    // of a query like their squared distances, with no epilogue arithmetic.
+    // Each lane keeps the top-2 of its candidates as 32-bit keys: that float
+    // with its low 4 bits replaced by the accumulator row r, compared as
+    // floats. A key is kept with min3 and med3; the tile of each kept key is
+    // recovered once per tile by comparing the keys with their values before
+    // the tile.
+    constexpr int kNoKey = 0x7F800000;   // +inf
+    int ka1 = kNoKey, ka2 = kNoKey, kb1 = kNoKey, kb2 = kNoKey;
     int ta1 = -1, ta2 = -1, tb1 = -1, tb2 = -1;
 
     // prefetch: thread t moves float4 number t + nt k (nt = 64 kW threads,
@@ -213,7 +240,7 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
     constexpr int kF = kCT * 32 / nt;   // float4 per thread per tile
     static_assert(kF * nt == kCT * 32, "the workgroup moves whole tiles");
     float4 pf[kF];
-    float pn = INFINITY;
+    float pn = kPadNorm;
     auto fetch = [&](uint32_t t0) {
         const float4* base = reinterpret_cast<const float4*>(B + (int64_t)t0 * 128);
         if (ce - t0 >= (uint32_t)kCT) {
@@ -225,7 +252,7 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             for (int k = 0; k < kF; ++k)
                 pf[k] = ((uint32_t)((tid + nt * k) >> 5) < ce - t0) ? base[tid + nt * k]
                                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (tid < kCT) pn = ((uint32_t)tid < ce - t0) ? nrmB[t0 + tid] : INFINITY;
+            if (tid < kCT) pn = ((uint32_t)tid < ce - t0) ? nrmB[t0 + tid] : kPadNorm;
         }
     };
     if (cb < ce) fetch(cb);
@@ -238,16 +265,21 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             const int r = f >> 5, c4 = f & 31;
             *reinterpret_cast<float4*>(&tile[r * kRow + c4 * 4]) = pf[k];
         }
-        if (tid < kCT) tnrm[tid] = pn;
+        if (tid < kCT) tnrm[tid] = 0.5f * pn;
         __syncthreads();
         if (ce - t0 > (uint32_t)kCT) fetch(t0 + kCT);
 
+        // rows of accumulator r in this lane: 8 (r / 4) + 4 h + r % 4
         floatx16 acc0, acc1;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            acc0[r] = -0.5f * na;
-            acc1[r] = -0.5f * nb;
+        for (int i = 0; i < 4; ++i) {
+            const float4 v = *reinterpret_cast<const float4*>(&tnrm[8 * i + 4 * h]);
+            acc0[4 * i] = v.x;
+            acc0[4 * i + 1] = v.y;
+            acc0[4 * i + 2] = v.z;
+            acc0[4 * i + 3] = v.w;
         }
+        acc1 = acc0;
         const float* trow = &tile[col * kRow + h * 64];
 #pragma unroll
         for (int i4 = 0; i4 < 16; ++i4) {
@@ -261,24 +293,28 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
             acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, qa[4 * i4 + 3], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, qb[4 * i4 + 3], acc1, 0, 0, 0);
         }
-        // result row (candidate) of accumulator r in this lane: 8 (r/4) + 4 h + r % 4;
-        // squared distance |b|^2 - 2 acc = |a|^2 + |b|^2 - 2 a.b
         const int pa1 = ka1, pa2 = ka2, pb1 = kb1, pb2 = kb2;
-        // two rows at a time: for k1 <= k2 and new keys x, y the two smallest
-        // of all four are min3(k1, x, y) and min(k2, med3(k1, x, y)) -- three
-        // instructions for two keys
+        // four rows at a time: for k1 <= k2 and new keys x, y the two smallest
+        // of all four are min3(k1, x, y) and min(k2, med3(k1, x, y)); two such
+        // steps share one min3 for k2 -- five instructions for four keys
 #pragma unroll
-        for (int r = 0; r < 16; r += 2) {
-            const float n0 = tnrm[8 * (r >> 2) + 4 * h + (r & 3)];
-            const float n1 = tnrm[8 * (r >> 2) + 4 * h + (r & 3) + 1];
-            const int xa = (__float_as_int(fmaf(-2.0f, acc0[r], n0)) & -16) | r;
-            const int ya = (__float_as_int(fmaf(-2.0f, acc0[r + 1], n1)) & -16) | (r + 1);
-            const int xb = (__float_as_int(fmaf(-2.0f, acc1[r], n0)) & -16) | r;
-            const int yb = (__float_as_int(fmaf(-2.0f, acc1[r + 1], n1)) & -16) | (r + 1);
-            ka2 = min(ka2, smed3(ka1, xa, ya));
-            ka1 = min(ka1, min(xa, ya));
-            kb2 = min(kb2, smed3(kb1, xb, yb));
-            kb1 = min(kb1, min(xb, yb));
+        for (int r = 0; r < 16; r += 4) {
+            const int xa = (__float_as_int(acc0[r]) & -16) | r;
+            const int ya = (__float_as_int(acc0[r + 1]) & -16) | (r + 1);
+            const int za = (__float_as_int(acc0[r + 2]) & -16) | (r + 2);
+            const int wa = (__float_as_int(acc0[r + 3]) & -16) | (r + 3);
+            const int xb = (__float_as_int(acc1[r]) & -16) | r;
+            const int yb = (__float_as_int(acc1[r + 1]) & -16) | (r + 1);
+            const int zb = (__float_as_int(acc1[r + 2]) & -16) | (r + 2);
+            const int wb = (__float_as_int(acc1[r + 3]) & -16) | (r + 3);
+            const int ma = fmed3_bits(ka1, xa, ya);
+            ka1 = fmin3_bits(ka1, xa, ya);
+            ka2 = fmin3_bits(ka2, ma, fmed3_bits(ka1, za, wa));
+            ka1 = fmin3_bits(ka1, za, wa);
+            const int mb = fmed3_bits(kb1, xb, yb);
+            kb1 = fmin3_bits(kb1, xb, yb);
+            kb2 = fmin3_bits(kb2, mb, fmed3_bits(kb1, zb, wb));
+            kb1 = fmin3_bits(kb1, zb, wb);
         }
         // A kept key equal to its value before the tile is that candidate; the
         // second key equal to the old first one is the old first candidate,
@@ -292,21 +328,21 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
         tb1 = (kb1 == pb1) ? tb1 : tt;
     }
 
-    // key -> (candidate index, score); padded rows (score +inf) and empty
-    // slots give index -1
-    auto unpack = [&](int k, int t, int& j, float& sc) {
-        const int bits = k & -16;
+    // key -> (candidate index, approximate squared distance |a|^2 + 2 key);
+    // padded rows (keys near kPadNorm / 2) and empty slots give index -1
+    auto unpack = [&](int k, int t, float nq2, int& j, float& sc) {
+        const float v = __int_as_float(k & -16);
         const int r = k & 15;
-        const bool real = t >= 0 && bits < 0x7F800000;
+        const bool real = t >= 0 && v < 0.25f * kPadNorm;
         j = real ? (int)cb + t + 8 * (r >> 2) + 4 * h + (r & 3) : -1;
-        sc = real ? __int_as_float(bits) : INFINITY;
+        sc = real ? fmaf(2.0f, v, nq2) : INFINITY;
     };
     if (q0 >= 0) {
         const int64_t o = (i0 * chunks + chunk) * kKeep + 2 * h;
         int j1, j2;
         float s1, s2;
-        unpack(ka1, ta1, j1, s1);
-        unpack(ka2, ta2, j2, s2);
+        unpack(ka1, ta1, na, j1, s1);
+        unpack(ka2, ta2, na, j2, s2);
         cidx[o] = j1; cidx[o + 1] = j2;
         cscore[o] = s1; cscore[o + 1] = s2;
     }
@@ -314,8 +350,8 @@ __device__ inline void topk_f32_item(const float* __restrict__ A, int64_t nq,
         const int64_t o = (i1 * chunks + chunk) * kKeep + 2 * h;
         int j1, j2;
         float s1, s2;
-        unpack(kb1, tb1, j1, s1);
-        unpack(kb2, tb2, j2, s2);
+        unpack(kb1, tb1, nb, j1, s1);
+        unpack(kb2, tb2, nb, j2, s2);
         cidx[o] = j1; cidx[o + 1] = j2;
         cscore[o] = s1; cscore[o + 1] = s2;
     }
