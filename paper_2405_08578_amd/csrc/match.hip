@@ -18,13 +18,14 @@
 //    registers while the current one is contracted; the candidate range is
 //    split into chunks so that the grid fills the chip.
 //  Each lane's top-2 of each chunk survives (4 candidates per query and
-//  chunk). The accumulator starts at -|a|^2 / 2, so |b|^2 - 2 acc is the
-//  squared distance itself (non-negative up to rounding); a lane keeps 32-bit
-//  keys (its bits with the low 4 replaced by the accumulator row) with a min
-//  and a med3, which costs ~4 VALU instructions per score instead of ~9 for
-//  (score, index) compare-selects -- VALU and MFMA work do not overlap on
-//  this part. The 4-bit truncation moves a score by at most 15 units in the
-//  last place, below the FP32 contraction's own rounding. The rescore kernel keeps the 4 best by contraction score,
+//  chunk). The queries are negated and the accumulator starts at |b|^2 / 2
+//  of its row, so it ends at |b|^2 / 2 - a.b = (|a - b|^2 - |a|^2) / 2, which
+//  orders a query's candidates like their squared distances; a lane keeps
+//  32-bit keys (its bits with the low 4 replaced by the accumulator row)
+//  with float min3 and med3, about 2.5 VALU instructions per score against
+//  ~9 for (score, index) compare-selects -- VALU and MFMA work do not
+//  overlap on this part. The 4-bit truncation moves a key by at most 15
+//  units in the last place, below the FP32 contraction's own rounding. The rescore kernel keeps the 4 best by contraction score,
 //  recomputes their squared distances directly in FP32, takes the two
 //  smallest (lowest index on ties) and applies d1 < ratio * d2 in double.
 //
@@ -130,15 +131,8 @@ __global__ __launch_bounds__(256) void sqnorm_kernel(const float* __restrict__ X
 
 // ---------------------------------------------------------------- FP32 path --
 
-// Medians of three integers (one VALU instruction each; the compiler does
-// not form them from min/max).
-__device__ inline int smed3(int a, int b, int c)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-
+// Median of three unsigned integers (one VALU instruction; the compiler
+// does not form it from min/max).
 __device__ inline uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
 {
     uint32_t r;
